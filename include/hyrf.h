@@ -1,0 +1,249 @@
+/*
+ * hyrf.h -- C ABI of the HyRF differentiable render step on AMD MI355X (gfx950).
+ *
+ * The method (Wang & Xu, "HyRF: Hybrid Radiance Fields for Memory-efficient
+ * and High-quality Novel View Synthesis"): explicit compact Gaussians are
+ * pre-culled against the camera (Sec. 3.3, Eqs. 8-9), their positions are
+ * contracted into (0,1)^3 (Sec. 3.2 Eq. 2, App. A.1) and looked up in two
+ * multi-resolution hash grids (Eq. 3) whose features two tiny MLPs decode
+ * into opacity / scale / rotation and view-dependent colour (Eqs. 4-6); the
+ * result is aggregated with the explicit parameters (Eq. 7), splatted with
+ * the 3DGS rasterizer -- EWA projection, depth-ordered tile binning,
+ * front-to-back alpha blending (Sec. 3.1, Eq. 1) -- and blended with a
+ * background colour that the radiance field predicts where each pixel's ray
+ * meets a sphere of radius r (Sec. 3.3 Eqs. 10-11, App. A.2).
+ *
+ * Conventions shared by every call
+ *  - Every pointer named in a descriptor or argument is DEVICE memory owned by
+ *    the caller, except the descriptor structs themselves, which are read on
+ *    the host during the call and may be freed when it returns.  The library
+ *    never allocates or frees device memory and keeps no state between calls
+ *    (apart from a thread-local error string).
+ *  - Work is enqueued asynchronously on `stream` (a hipStream_t passed as
+ *    void*; NULL = the default stream).  Inputs must stay valid, and outputs
+ *    must not be read, until the stream has reached the work.
+ *  - Arrays are float32 and planar (structure of arrays) unless stated.
+ *    "n" is the Gaussian count, "V" the number of views, "L" the number of
+ *    grid levels.  All views of one call share width and height.
+ *  - Every argument is validated on the host before anything is enqueued;
+ *    on failure nothing is launched or written, the call returns a non-zero
+ *    hyrf_status and hyrf_last_error() describes the problem.  Device-side
+ *    faults surface at the caller's next synchronisation.  NaN/Inf inputs
+ *    propagate; they are not checked.
+ */
+#ifndef HYRF_H
+#define HYRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HYRF_TILE 16          /* screen tiles are 16 x 16 pixels */
+#define HYRF_MAX_VIEWS 8
+#define HYRF_PE_OCTAVES 4     /* view-direction encoding: 4 octaves, sin and cos -> 24 inputs */
+#define HYRF_GEO_OUT 8        /* geometry decoder: opacity, scale[3], rotation[4] */
+#define HYRF_COL_OUT 3        /* colour decoder: rgb */
+
+typedef enum {
+  HYRF_OK = 0,
+  HYRF_ERR_INVALID_ARGUMENT = 1,
+  HYRF_ERR_UNSUPPORTED = 2,
+  HYRF_ERR_CAPACITY = 3,
+  HYRF_ERR_LAUNCH = 4
+} hyrf_status;
+
+typedef enum { HYRF_F32 = 0, HYRF_F16 = 1, HYRF_BF16 = 2 } hyrf_dtype;
+/* RENDER: the background is added only where the final transmittance
+ * exceeds tau_T (Sec. 3.3, last paragraph) and nothing is saved.
+ * TRAIN: the background is added at every pixel and the state the backward
+ * needs is saved. */
+typedef enum { HYRF_RENDER = 0, HYRF_TRAIN = 1 } hyrf_mode;
+
+/* Explicit compact Gaussians (Sec. 3.2, first paragraph). */
+typedef struct {
+  int32_t n;
+  const float* pos;      /* [3][n] world position p_e                              */
+  const float* scale_e;  /* [3][n] scale logit s_e (paper: one value; pass equal axes) */
+  const float* rot_e;    /* [4][n] rotation residual (w,x,y,z) or NULL (paper: none) */
+  const float* opac_e;   /* [n]    opacity logit alpha_e                           */
+  const float* col_e;    /* [3][n] colour logit c_e                                */
+} hyrf_gaussians;
+
+/* Two hash-grid fields and their decoders (Sec. 3.2, Eqs. 2-6; Sec. 4.1). */
+typedef struct {
+  int32_t levels;        /* L: 4, 8, 12 or 16                                       */
+  int32_t features;      /* F: must be 2                                           */
+  int32_t log2_T_geo;    /* geometry table rows per level, 2^log2_T_geo (10..24)    */
+  int32_t log2_T_rad;    /* radiance table rows per level (10..24)                  */
+  float base_res;        /* N_min (>= 2); N_l = floor(N_min * growth^l)             */
+  float growth;          /* b (>= 1)                                               */
+  int32_t table_dtype;   /* HYRF_F32 or HYRF_F16                                   */
+  const void* table_geo; /* [L][T_geo][2]                                          */
+  const void* table_rad; /* [L][T_rad][2]                                          */
+  int32_t hidden;        /* MLP width: 16, 32, 48 or 64                            */
+  int32_t n_hidden;      /* hidden layers: 1 or 2 (ReLU, no bias)                  */
+  int32_t mlp_dtype;     /* HYRF_F32, or HYRF_BF16 (bf16 operands, fp32 accumulate; the
+                            weights are still passed as float32 and rounded on load) */
+  const float* mlp_geo;  /* layers concatenated, each row-major [out][in]:
+                            [hidden][2L], ([hidden][hidden]), [8][hidden]            */
+  const float* mlp_col;  /* [hidden][2L+24], ([hidden][hidden]), [3][hidden]        */
+  float aabb_center[3];  /* scene box: p' = (p - centre) * inv_half (App. A.1 Eq. 13) */
+  float aabb_inv_half[3];
+  float bg_radius;       /* background sphere radius r (Sec. 4.1: 100)              */
+  float tau_T;           /* render-mode background threshold (Sec. 4.1: 0.2)        */
+} hyrf_fields;
+
+/* Pinhole camera, world -> camera p_c = R p + t (Sec. 3.3 Eq. 8), OpenCV axes
+ * (x right, y down, z forward); pixel (x, y) is sampled at (x+.5, y+.5). */
+typedef struct {
+  float R[9];            /* row-major */
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t width, height;
+  float z_near;          /* pre-cull: drop Gaussians with depth <= z_near            */
+  float cull_tol;        /* pre-cull tolerance band "tol" of Eq. 9                   */
+} hyrf_camera;
+
+/* Output of hyrf_query_fields: the union (over views) of pre-cull survivors,
+ * compacted in ascending Gaussian index, with their aggregated properties.
+ * Slot k (0 <= k < *vis_count) describes Gaussian vis_idx[k]. */
+typedef struct {
+  int32_t* vis_count;    /* [1]                                                     */
+  int32_t* vis_idx;      /* [n]                                                     */
+  float* opacity;        /* [n]       sigmoid(a_n + a_e)                             */
+  float* scale;          /* [3][n]    sigmoid(s_n + s_e)                             */
+  float* quat;           /* [4][n]    Normalize(r_n (+ r_e)), (w,x,y,z)               */
+  float* rgb;            /* [V][3][n] sigmoid(c_n + c_e) per view                    */
+  float* feat_geo;       /* [n][2L] encoded geometry features, or NULL (TRAIN needs it) */
+  float* feat_rad;       /* [n][2L] encoded radiance features, or NULL (TRAIN needs it) */
+  uint32_t* dbg_index;   /* optional [n][2][L][8] table rows (field 0 = geometry,
+                            corner k = dx + 2 dy + 4 dz), or NULL                    */
+} hyrf_query_out;
+
+/* Per (view, slot) splat records written by hyrf_project and read by
+ * hyrf_bin_sort / hyrf_composite / hyrf_render_backward. */
+typedef struct {
+  int32_t n_max;         /* slots per view (>= *count; normally n)                   */
+  const int32_t* count;  /* [1] valid slots (normally hyrf_query_out.vis_count)       */
+  float* rec;            /* [V][n_max][12]: u, v, conic a, b, c, opacity, r, g, b,
+                            depth, 0, 0  (float4-aligned; 16-byte aligned pointer)    */
+  int32_t* rect;         /* [V][n_max][4]: tile rectangle x0, y0, x1, y1 (x1, y1
+                            exclusive); empty when the splat is culled in this view,
+                            degenerate, or cannot reach alpha 1/255 anywhere           */
+  float* depth;          /* [V][n_max] camera depth rounded to float32 (> 0): ordering key */
+  int64_t* total;        /* [1] sum of rectangle areas = tile entries (written by
+                            hyrf_project)                                           */
+} hyrf_splats;
+
+/* Gradient accumulators (+=) -- all float32, caller-zeroed, same layouts as
+ * the corresponding inputs.  Any pointer may be NULL to skip that output. */
+typedef struct {
+  float* pos;            /* [3][n] */
+  float* scale_e;        /* [3][n] */
+  float* rot_e;          /* [4][n] (ignored when hyrf_gaussians.rot_e is NULL) */
+  float* opac_e;         /* [n]    */
+  float* col_e;          /* [3][n] */
+  float* table_geo;      /* [L][T_geo][2] float32 even for float16 tables */
+  float* table_rad;      /* [L][T_rad][2] */
+  float* mlp_geo;        /* same layout as hyrf_fields.mlp_geo */
+  float* mlp_col;        /* same layout as hyrf_fields.mlp_col */
+} hyrf_grads;
+
+/* Forward state of a TRAIN-mode render that hyrf_render_backward reads. */
+typedef struct {
+  const hyrf_query_out* query;   /* with feat_geo / feat_rad filled              */
+  const hyrf_splats* splats;
+  const uint32_t* vals;          /* sorted splat ids from hyrf_bin_sort            */
+  const uint32_t* tile_ranges;   /* [V*tiles][2]                                  */
+  const float* T_final;          /* [V][H][W] from hyrf_composite                 */
+  const int32_t* last;           /* [V][H][W] from hyrf_composite                 */
+  const float* bg_rgb;           /* [V][3][H][W] background colours c_s           */
+} hyrf_fwd_state;
+
+/* ---- the render step ------------------------------------------------------ */
+
+/* Pre-cull, field query, decoding and aggregation (Sec. 3.3 Eqs. 8-9, then
+ * Sec. 3.2 Eqs. 2-7).  A Gaussian survives if, in at least one of the V
+ * views, its camera depth exceeds z_near and its projected centre lies in the
+ * image frame widened by cull_tol on every side (normalised coordinates).
+ * The survivors are queried once in both fields; the colour decoder runs once
+ * per view with that view's direction encoding.  ws: workspace of at least
+ * hyrf_query_workspace_bytes(n) bytes (16-byte aligned). */
+hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g,
+                              const hyrf_camera* cams, int32_t n_views,
+                              const hyrf_query_out* out, void* ws, size_t ws_bytes,
+                              void* stream);
+
+/* EWA projection of every surviving Gaussian into every view (3DGS
+ * rasterizer, Sec. 3.1): 2D covariance J W Sigma W^T J^T + 0.3 I, conic,
+ * centre, float32 depth key, and a conservative tile rectangle holding every
+ * pixel where alpha >= 1/255 can hold.  Also writes splats->total. */
+hyrf_status hyrf_project(const hyrf_gaussians* g, const hyrf_query_out* q,
+                         const hyrf_camera* cams, int32_t n_views,
+                         const hyrf_splats* splats, void* stream);
+
+/* Tile binning and depth ordering (Sec. 3.1, "ordered by depth"): every
+ * splat is listed once for each tile its rectangle covers, ordered by
+ * (view, tile, float32 depth, slot).  vals[e] = view * n_max + slot of entry
+ * e; keys[e] = view * tiles + tile (keys may be NULL); tile_ranges[2k],
+ * [2k+1] = first / one-past-last entry of tile k = view*tiles + ty*tiles_x + tx.
+ * capacity = length of keys / vals; returns HYRF_ERR_CAPACITY (nothing
+ * launched) when n_entries > capacity, where n_entries is the caller's copy
+ * of *splats->total (the one host read of the step). */
+hyrf_status hyrf_bin_sort(const hyrf_splats* splats, const hyrf_camera* cams,
+                          int32_t n_views, int64_t n_entries, int64_t capacity,
+                          uint32_t* keys, uint32_t* vals, uint32_t* tile_ranges,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Front-to-back alpha blending per 16x16 tile (Eq. 1 with the 3DGS rules:
+ * alpha = min(0.99, o exp(-d^T conic d / 2)), skipped below 1/255, stop before
+ * the transmittance falls below 1e-4), then the background
+ * C = C_fg + T_final * c_s with c_s = sigmoid(colour decoder(Theta_rad at the
+ * ray / sphere intersection, PE(ray direction))) (Sec. 3.3 Eqs. 10-11).
+ * out_rgb [V][3][H][W]; out_T [V][H][W]; in TRAIN mode out_last [V][H][W]
+ * (entries consumed up to the last contributor) and out_bg [V][3][H][W] are
+ * required, in RENDER mode they may be NULL.  ws: at least
+ * hyrf_composite_workspace_bytes(V, W, H) bytes. */
+hyrf_status hyrf_composite(const hyrf_splats* splats, const uint32_t* vals,
+                           const uint32_t* tile_ranges, const hyrf_camera* cams,
+                           int32_t n_views, const hyrf_fields* fields, int32_t mode,
+                           float* out_rgb, float* out_T, int32_t* out_last, float* out_bg,
+                           void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of the whole step: given dL/dC [V][3][H][W], accumulates (+=) the
+ * gradients of every explicit parameter, both hash tables (background uses
+ * included) and both decoders' weights.  Predicates (pre-cull, alpha
+ * threshold, early stop, tau_T) and grid-cell choices are held fixed; the
+ * 0.99 alpha clamp passes no gradient where it is active.  ws: at least
+ * hyrf_backward_workspace_bytes(...) bytes. */
+hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians* g,
+                                 const hyrf_camera* cams, int32_t n_views,
+                                 const hyrf_fwd_state* saved, const float* dL_drgb,
+                                 const hyrf_grads* grads, void* ws, size_t ws_bytes,
+                                 void* stream);
+
+/* L1 photometric term of the training loss (Sec. 3.4 Eq. 12, lambda = 0):
+ * loss[0] = mean |img - target| over n values, grad[i] = sign(img - target)/n
+ * (sign(0) = 0).  loss and grad are device pointers; grad may be NULL. */
+hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n,
+                         float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
+
+/* ---- sizing and errors ----------------------------------------------------- */
+size_t hyrf_query_workspace_bytes(int32_t n);
+size_t hyrf_bin_sort_workspace_bytes(int32_t n_views, int32_t n_max, int64_t capacity,
+                                     int32_t width, int32_t height);
+size_t hyrf_composite_workspace_bytes(int32_t n_views, int32_t width, int32_t height);
+size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max);
+size_t hyrf_l1_workspace_bytes(int64_t n);
+/* Message of the last failed call on this thread ("" if none). */
+const char* hyrf_last_error(void);
+/* Library version string. */
+const char* hyrf_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HYRF_H */

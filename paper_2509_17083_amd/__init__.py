@@ -1,0 +1,12 @@
+"""HyRF differentiable render step for AMD MI355X (gfx950).
+
+The computation lives in lib/libhyrf.so (hand-written HIP kernels behind the
+C ABI of include/hyrf.h); this package only marshals torch device buffers
+into those calls.
+"""
+from . import _abi
+from .render import (BF16, F16, F32, RENDER, TRAIN, DeviceScene, ForwardState, Workspace, bin_sort,
+                     c_cameras, composite, l1_loss, project, query_fields, render)
+
+__all__ = ["DeviceScene", "ForwardState", "Workspace", "render", "query_fields", "project", "bin_sort",
+           "composite", "l1_loss", "c_cameras", "RENDER", "TRAIN", "F32", "F16", "BF16"]

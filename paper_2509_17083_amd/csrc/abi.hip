@@ -1,0 +1,348 @@
+// C ABI of the HyRF render step: host-side validation, workspace carving
+// and kernel launches.  No allocation, no global state except the
+// thread-local error string.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+
+#include <string>
+
+#include "backward.h"
+#include "bin.h"
+#include "block.h"
+#include "composite.h"
+#include "kernels.h"
+#include "project.h"
+#include "query.h"
+
+using namespace hyrf;
+
+namespace {
+
+thread_local std::string g_err;
+
+hyrf_status fail(hyrf_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return s;
+}
+
+hyrf_status launch_error(hipError_t e) {
+  return fail(HYRF_ERR_LAUNCH, "kernel launch failed: %s", hipGetErrorString(e));
+}
+
+#define REQ(cond, ...)                                                  \
+  do {                                                                  \
+    if (!(cond)) return fail(HYRF_ERR_INVALID_ARGUMENT, __VA_ARGS__);   \
+  } while (0)
+
+hyrf_status check_launch() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return launch_error(e);
+  g_err.clear();
+  return HYRF_OK;
+}
+
+hyrf_status check_cams(const hyrf_camera* cams, int V) {
+  REQ(cams, "cams is NULL");
+  REQ(V >= 1 && V <= HYRF_MAX_VIEWS, "n_views = %d outside [1, %d]", V, HYRF_MAX_VIEWS);
+  for (int v = 0; v < V; ++v) {
+    const hyrf_camera& c = cams[v];
+    REQ(c.width > 0 && c.height > 0, "camera %d: width/height must be positive", v);
+    REQ(c.width == cams[0].width && c.height == cams[0].height, "camera %d: all views must share width and height", v);
+    REQ((int64_t)c.width * c.height * V < (int64_t)1 << 31, "image too large");
+    REQ(c.fx > 0.f && c.fy > 0.f, "camera %d: focal lengths must be positive", v);
+    REQ(c.z_near > 0.f, "camera %d: z_near must be positive", v);
+    REQ(c.cull_tol >= 0.f, "camera %d: cull_tol must be >= 0", v);
+  }
+  return HYRF_OK;
+}
+
+Cams make_cams(const hyrf_camera* cams, int V) {
+  Cams c{};
+  for (int v = 0; v < V; ++v) c.c[v] = to_camp(cams[v]);
+  c.V = V;
+  return c;
+}
+
+hyrf_status check_gauss(const hyrf_gaussians* g) {
+  REQ(g, "gaussians is NULL");
+  REQ(g->n >= 0, "gaussian count must be >= 0");
+  if (g->n > 0) REQ(g->pos && g->scale_e && g->opac_e && g->col_e, "a gaussian array is NULL");
+  return HYRF_OK;
+}
+
+hyrf_status check_fields(const hyrf_fields* f) {
+  REQ(f, "fields is NULL");
+  REQ(f->levels == 4 || f->levels == 8 || f->levels == 12 || f->levels == 16, "levels = %d must be 4, 8, 12 or 16", f->levels);
+  REQ(f->features == 2, "features per entry must be 2");
+  REQ(f->log2_T_geo >= 10 && f->log2_T_geo <= 24 && f->log2_T_rad >= 10 && f->log2_T_rad <= 24,
+      "log2 table sizes must be in [10, 24]");
+  REQ(f->base_res >= 2.f && f->growth >= 1.f, "base_res must be >= 2 and growth >= 1");
+  REQ(f->table_geo && f->table_rad && f->mlp_geo && f->mlp_col, "a field array is NULL");
+  REQ(f->hidden == 16 || f->hidden == 32 || f->hidden == 48 || f->hidden == 64, "hidden width must be 16, 32, 48 or 64");
+  REQ(f->n_hidden == 1 || f->n_hidden == 2, "n_hidden must be 1 or 2");
+  REQ(f->bg_radius > 0.f, "bg_radius must be positive");
+  for (int d = 0; d < 3; ++d) REQ(f->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
+  if (!(f->table_dtype == HYRF_F32))
+    return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported", f->table_dtype);
+  if (!(f->mlp_dtype == HYRF_F32))
+    return fail(HYRF_ERR_UNSUPPORTED, "mlp dtype %d not supported", f->mlp_dtype);
+  if (!shape_supported(f->levels, f->hidden, f->n_hidden))
+    return fail(HYRF_ERR_UNSUPPORTED, "no kernel for levels=%d hidden=%d n_hidden=%d "
+                "(built: 16/64/2, 16/64/1, 8/32/1, 8/64/2)", f->levels, f->hidden, f->n_hidden);
+  return HYRF_OK;
+}
+
+GridP make_grid(const hyrf_fields* f) {
+  GridP g{};
+  g.L = f->levels;
+  g.log2_T_geo = f->log2_T_geo;
+  g.log2_T_rad = f->log2_T_rad;
+  g.mask_geo = (1u << f->log2_T_geo) - 1u;
+  g.mask_rad = (1u << f->log2_T_rad) - 1u;
+  double s = (double)f->base_res;
+  for (int l = 0; l < f->levels; ++l) {
+    int res = (int)floor(s);
+    g.res[l] = res;
+    double side = (double)res + 1.0;
+    if (side * side * side <= (double)(1u << f->log2_T_geo)) g.dense_geo |= 1u << l;
+    if (side * side * side <= (double)(1u << f->log2_T_rad)) g.dense_rad |= 1u << l;
+    s = s * (double)f->growth;
+  }
+  for (int d = 0; d < 3; ++d) {
+    g.center[d] = f->aabb_center[d];
+    g.inv_half[d] = f->aabb_inv_half[d];
+  }
+  g.bg_radius = f->bg_radius;
+  g.tau_T = f->tau_T;
+  return g;
+}
+
+size_t query_ws(int n, uint32_t** flag, uint32_t** pos, uint32_t** temp, void* base) {
+  Carve c(base);
+  uint32_t* a = c.take<uint32_t>(n > 0 ? n : 1);
+  uint32_t* b = c.take<uint32_t>(n > 0 ? n : 1);
+  uint32_t* t = c.take<uint32_t>(scan_temp_elems(n));
+  if (flag) *flag = a;
+  if (pos) *pos = b;
+  if (temp) *temp = t;
+  return c.off;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hyrf_last_error(void) { return g_err.c_str(); }
+const char* hyrf_version(void) { return "hyrf-gfx950 0.1"; }
+
+size_t hyrf_query_workspace_bytes(int32_t n) { return query_ws(n, nullptr, nullptr, nullptr, nullptr); }
+
+hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g,
+                              const hyrf_camera* cams, int32_t n_views, const hyrf_query_out* out,
+                              void* ws, size_t ws_bytes, void* stream) {
+  hyrf_status s;
+  if ((s = check_fields(fields)) != HYRF_OK) return s;
+  if ((s = check_gauss(g)) != HYRF_OK) return s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  REQ(out && out->vis_count && out->vis_idx, "query output: vis_count / vis_idx is NULL");
+  REQ(g->n == 0 || (out->opacity && out->scale && out->quat && out->rgb), "query output: a property array is NULL");
+  REQ((out->feat_geo == nullptr) == (out->feat_rad == nullptr), "feat_geo and feat_rad must both be set or both NULL");
+  const size_t need = hyrf_query_workspace_bytes(g->n);
+  REQ(ws && ws_bytes >= need, "query workspace too small: %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  uint32_t *flag, *pos, *temp;
+  query_ws(g->n, &flag, &pos, &temp, ws);
+  const Cams cc = make_cams(cams, n_views);
+  launch_cull(g->pos, g->n, cc, flag, pos, temp, out->vis_idx, out->vis_count, st);
+  if (g->n > 0) {
+    QueryArgs a{};
+    a.grid = make_grid(fields);
+    a.cams = cc;
+    a.table_geo = (const float*)fields->table_geo;
+    a.table_rad = (const float*)fields->table_rad;
+    a.w_geo = fields->mlp_geo;
+    a.w_col = fields->mlp_col;
+    a.n = g->n;
+    a.count = out->vis_count;
+    a.vis_idx = out->vis_idx;
+    a.pos = g->pos;
+    a.scale_e = g->scale_e;
+    a.rot_e = g->rot_e;
+    a.opac_e = g->opac_e;
+    a.col_e = g->col_e;
+    a.opacity = out->opacity;
+    a.scale = out->scale;
+    a.quat = out->quat;
+    a.rgb = out->rgb;
+    a.feat_geo = out->feat_geo;
+    a.feat_rad = out->feat_rad;
+    a.dbg = out->dbg_index;
+    launch_query(fields->levels, fields->hidden, fields->n_hidden, a, g->n, st);
+  }
+  return check_launch();
+}
+
+hyrf_status hyrf_project(const hyrf_gaussians* g, const hyrf_query_out* q, const hyrf_camera* cams,
+                         int32_t n_views, const hyrf_splats* sp, void* stream) {
+  hyrf_status s;
+  if ((s = check_gauss(g)) != HYRF_OK) return s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  REQ(q && q->vis_count && q->vis_idx && q->opacity && q->scale && q->quat && q->rgb, "query output incomplete");
+  REQ(sp && sp->rec && sp->rect && sp->depth && sp->total, "splats: an array is NULL");
+  REQ(sp->n_max >= g->n, "splats.n_max (%d) must be >= the gaussian count (%d)", sp->n_max, g->n);
+  REQ(((uintptr_t)sp->rec & 15) == 0 && ((uintptr_t)sp->rect & 15) == 0, "splats.rec / rect must be 16-byte aligned");
+  ProjArgs a{};
+  a.cams = make_cams(cams, n_views);
+  a.n = g->n;
+  a.n_max = sp->n_max;
+  a.tiles_x = (cams[0].width + TILE - 1) / TILE;
+  a.tiles_y = (cams[0].height + TILE - 1) / TILE;
+  a.count = q->vis_count;
+  a.vis_idx = q->vis_idx;
+  a.pos = g->pos;
+  a.opacity = q->opacity;
+  a.scale = q->scale;
+  a.quat = q->quat;
+  a.rgb = q->rgb;
+  a.rec = sp->rec;
+  a.rect = sp->rect;
+  a.depth = sp->depth;
+  a.total = sp->total;
+  launch_project(a, g->n, n_views, (hipStream_t)stream);
+  return check_launch();
+}
+
+size_t hyrf_bin_sort_workspace_bytes(int32_t n_views, int32_t n_max, int64_t capacity, int32_t width,
+                                     int32_t height) {
+  const int tiles = ((width + TILE - 1) / TILE) * ((height + TILE - 1) / TILE);
+  return carve_bin_ws(nullptr, n_views, n_max, capacity, tiles * n_views).bytes;
+}
+
+hyrf_status hyrf_bin_sort(const hyrf_splats* sp, const hyrf_camera* cams, int32_t n_views,
+                          int64_t n_entries, int64_t capacity, uint32_t* keys, uint32_t* vals,
+                          uint32_t* tile_ranges, void* ws, size_t ws_bytes, void* stream) {
+  hyrf_status s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  REQ(sp && sp->count && sp->rect && sp->depth, "splats: count / rect / depth is NULL");
+  REQ(sp->n_max >= 0, "splats.n_max must be >= 0");
+  REQ(((uintptr_t)sp->rect & 15) == 0, "splats.rect must be 16-byte aligned");
+  REQ(vals && tile_ranges, "vals / tile_ranges is NULL");
+  REQ(n_entries >= 0 && capacity >= 0, "n_entries / capacity must be >= 0");
+  REQ((int64_t)n_views * sp->n_max < ((int64_t)1 << 31), "too many splats");
+  if (n_entries > capacity)
+    return fail(HYRF_ERR_CAPACITY, "tile entries %lld exceed capacity %lld", (long long)n_entries, (long long)capacity);
+  if (n_entries >= ((int64_t)1 << 31)) return fail(HYRF_ERR_CAPACITY, "more than 2^31 - 1 tile entries");
+  const int tx = (cams[0].width + TILE - 1) / TILE, ty = (cams[0].height + TILE - 1) / TILE;
+  const size_t need = hyrf_bin_sort_workspace_bytes(n_views, sp->n_max, capacity, cams[0].width, cams[0].height);
+  REQ(ws && ws_bytes >= need, "bin_sort workspace too small: %zu < %zu bytes", ws_bytes, need);
+  BinWs w = carve_bin_ws(ws, n_views, sp->n_max, capacity, tx * ty * n_views);
+  BinArgs a{};
+  a.V = n_views;
+  a.n_max = sp->n_max;
+  a.tiles_x = tx;
+  a.tiles_y = ty;
+  a.count = sp->count;
+  a.depth = sp->depth;
+  a.rect = sp->rect;
+  a.n_entries = n_entries;
+  a.keys = keys;
+  a.vals = vals;
+  a.ranges = tile_ranges;
+  launch_bin_sort(a, w, (hipStream_t)stream);
+  return check_launch();
+}
+
+size_t hyrf_composite_workspace_bytes(int32_t n_views, int32_t width, int32_t height) {
+  Carve c(nullptr);
+  c.take<uint32_t>((size_t)n_views * width * height);
+  c.take<uint32_t>(1);
+  return c.off;
+}
+
+hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const uint32_t* tile_ranges,
+                           const hyrf_camera* cams, int32_t n_views, const hyrf_fields* fields,
+                           int32_t mode, float* out_rgb, float* out_T, int32_t* out_last, float* out_bg,
+                           void* ws, size_t ws_bytes, void* stream) {
+  hyrf_status s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  REQ(mode == HYRF_RENDER || mode == HYRF_TRAIN, "mode must be HYRF_RENDER or HYRF_TRAIN");
+  REQ(sp && sp->rec, "splats.rec is NULL");
+  REQ(sp->n_max >= 0 && (int64_t)n_views * sp->n_max < ((int64_t)1 << 31), "splats.n_max out of range");
+  REQ(((uintptr_t)sp->rec & 15) == 0, "splats.rec must be 16-byte aligned");
+  REQ(vals && tile_ranges && out_rgb && out_T, "vals / tile_ranges / out_rgb / out_T is NULL");
+  if (mode == HYRF_TRAIN) REQ(out_last && (out_bg || !fields), "TRAIN mode needs out_last and out_bg");
+  if (fields && (s = check_fields(fields)) != HYRF_OK) return s;
+  const int W = cams[0].width, H = cams[0].height;
+  const size_t need = hyrf_composite_workspace_bytes(n_views, W, H);
+  REQ(ws && ws_bytes >= need, "composite workspace too small: %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  Carve c(ws);
+  uint32_t* list = c.take<uint32_t>((size_t)n_views * W * H);
+  uint32_t* list_count = c.take<uint32_t>(1);
+  CompArgs a{};
+  a.W = W;
+  a.H = H;
+  a.tiles_x = (W + TILE - 1) / TILE;
+  a.tiles_y = (H + TILE - 1) / TILE;
+  a.rec = sp->rec;
+  a.n_rec = (uint32_t)((int64_t)n_views * sp->n_max);
+  a.vals = vals;
+  a.ranges = tile_ranges;
+  a.tau_T = fields ? fields->tau_T : 0.f;
+  a.out_rgb = out_rgb;
+  a.out_T = out_T;
+  a.out_last = out_last;
+  const bool render_bg = fields && mode == HYRF_RENDER;
+  a.list = render_bg ? list : nullptr;
+  a.list_count = render_bg ? list_count : nullptr;
+  launch_composite(a, n_views, st);
+  if (fields) {
+    BgArgs b{};
+    b.grid = make_grid(fields);
+    b.cams = make_cams(cams, n_views);
+    b.table_rad = (const float*)fields->table_rad;
+    b.w_col = fields->mlp_col;
+    b.W = W;
+    b.H = H;
+    b.list = render_bg ? list : nullptr;
+    b.list_count = render_bg ? list_count : nullptr;
+    b.T = out_T;
+    b.out_rgb = out_rgb;
+    b.bg_save = mode == HYRF_TRAIN ? out_bg : nullptr;
+    launch_bg(fields->levels, fields->hidden, fields->n_hidden, b, n_views * W * H, st);
+  }
+  return check_launch();
+}
+
+size_t hyrf_l1_workspace_bytes(int64_t n) { return l1_ws_elems(n) * sizeof(float); }
+
+hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n, float* loss, float* grad,
+                         void* ws, size_t ws_bytes, void* stream) {
+  REQ(img && target && loss, "img / target / loss is NULL");
+  REQ(n > 0, "n must be positive");
+  REQ(ws && ws_bytes >= hyrf_l1_workspace_bytes(n), "l1 workspace too small");
+  launch_l1(img, target, n, loss, grad, (float*)ws, (hipStream_t)stream);
+  return check_launch();
+}
+
+size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max) {
+  (void)fields; (void)n_views; (void)n_max;
+  return 256;
+}
+
+hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians* g,
+                                 const hyrf_camera* cams, int32_t n_views, const hyrf_fwd_state* saved,
+                                 const float* dL_drgb, const hyrf_grads* grads, void* ws,
+                                 size_t ws_bytes, void* stream) {
+  (void)fields; (void)g; (void)cams; (void)n_views; (void)saved; (void)dL_drgb; (void)grads;
+  (void)ws; (void)ws_bytes; (void)stream;
+  return fail(HYRF_ERR_UNSUPPORTED, "backward not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// Tile binning with depth ordering.
+//
+// Instead of sorting (tile | depth) keys of every tile entry, the splats are
+// sorted once by their float32 depth (stable, so equal depths keep slot
+// order), the entries are then written out in that depth order, and a
+// stable sort by the small (view, tile) key groups them per tile while
+// keeping depth order inside every tile.  The result equals an ordering of
+// entries by (view, tile, depth, slot); the wide sort runs over splats (1M)
+// and only a 16-bit sort runs over entries.
+#include "bin.h"
+#include "block.h"
+#include "kernels.h"
+
+namespace hyrf {
+
+// depth keys of every (view, slot); slots without tiles sort last
+__global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ depth,
+                                                    const int4* __restrict__ rect,
+                                                    const int32_t* __restrict__ count, int n_max,
+                                                    int64_t m, uint32_t* __restrict__ key,
+                                                    uint32_t* __restrict__ val) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  const int slot = (int)(i % n_max);
+  uint32_t k = 0xFFFFFFFFu;
+  if (slot < *count) {
+    const int4 r = rect[i];
+    if (r.z > r.x && r.w > r.y) k = __float_as_uint(depth[i]);
+  }
+  key[i] = k;
+  val[i] = (uint32_t)i;
+}
+
+// number of tile entries of the splat at each depth-sorted position
+__global__ __launch_bounds__(256) void k_tile_counts(const uint32_t* __restrict__ skey,
+                                                     const uint32_t* __restrict__ sval,
+                                                     const int4* __restrict__ rect, int64_t m,
+                                                     uint32_t* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  uint32_t c = 0;
+  if (skey[i] != 0xFFFFFFFFu) {
+    const int4 r = rect[sval[i]];
+    c = (uint32_t)((r.z - r.x) * (r.w - r.y));
+  }
+  cnt[i] = c;
+}
+
+// write the entries of each splat in depth order: key = view*tiles + tile
+__global__ __launch_bounds__(256) void k_dup(const uint32_t* __restrict__ skey,
+                                             const uint32_t* __restrict__ sval,
+                                             const int4* __restrict__ rect,
+                                             const uint32_t* __restrict__ off, int64_t m, int n_max,
+                                             int tiles_x, int tiles, int64_t capacity,
+                                             uint32_t* __restrict__ ekey, uint32_t* __restrict__ eval) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m || skey[i] == 0xFFFFFFFFu) return;
+  const uint32_t id = sval[i];
+  const int4 r = rect[id];
+  const uint32_t vbase = (id / (uint32_t)n_max) * (uint32_t)tiles;
+  uint64_t o = off[i];
+  for (int ty = r.y; ty < r.w; ++ty)
+    for (int tx = r.x; tx < r.z; ++tx) {
+      if ((int64_t)o < capacity) {
+        ekey[o] = vbase + (uint32_t)(ty * tiles_x + tx);
+        eval[o] = id;
+      }
+      ++o;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key, int64_t ne,
+                                                uint32_t nkeys, uint32_t* __restrict__ ranges) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= ne) return;
+  const uint32_t k = key[e];
+  if (k >= nkeys) return;   // only reachable when n_entries disagrees with the device total
+  if (e == 0 || key[e - 1] != k) ranges[2 * (size_t)k] = (uint32_t)e;
+  if (e == ne - 1 || key[e + 1] != k) ranges[2 * (size_t)k + 1] = (uint32_t)(e + 1);
+}
+
+__global__ __launch_bounds__(256) void k_zero_words(uint32_t* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+BinWs carve_bin_ws(void* ws, int V, int n_max, int64_t capacity, int tiles_total) {
+  Carve c(ws);
+  BinWs w;
+  const int64_t m = (int64_t)V * n_max;
+  w.dk[0] = c.take<uint32_t>(m);
+  w.dk[1] = c.take<uint32_t>(m);
+  w.dv[0] = c.take<uint32_t>(m);
+  w.dv[1] = c.take<uint32_t>(m);
+  w.cnt = c.take<uint32_t>(m);
+  w.ek[0] = c.take<uint32_t>(capacity > 0 ? capacity : 1);
+  w.ek[1] = c.take<uint32_t>(capacity > 0 ? capacity : 1);
+  w.ev = c.take<uint32_t>(capacity > 0 ? capacity : 1);
+  int64_t big = m > capacity ? m : capacity;
+  w.temp = c.take<uint32_t>(radix_temp_elems(big) + scan_temp_elems(m));
+  w.bytes = c.off;
+  (void)tiles_total;
+  return w;
+}
+
+int key_bits_for(int64_t nkeys) {
+  int b = 0;
+  while (((int64_t)1 << b) < nkeys) ++b;
+  return b;
+}
+
+void launch_bin_sort(const BinArgs& a, const BinWs& w, hipStream_t st) {
+  const int64_t m = (int64_t)a.V * a.n_max;
+  const int tiles = a.tiles_x * a.tiles_y;
+  const int64_t nranges = 2 * (int64_t)a.V * tiles;
+  // 1. depth order of all splats (stable)
+  k_depth_keys<<<nblk(m), 256, 0, st>>>(a.depth, reinterpret_cast<const int4*>(a.rect), a.count,
+                                        a.n_max, m, w.dk[0], w.dv[0]);
+  uint32_t* dk[2] = {w.dk[0], w.dk[1]};
+  uint32_t* dv[2] = {w.dv[0], w.dv[1]};
+  const int dcur = radix_sort_pairs(dk, dv, 0, m, 32, w.temp, st);
+  // 2. entry offsets in depth order
+  k_tile_counts<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), m, w.cnt);
+  scan_exclusive_u32(w.cnt, w.cnt, m, w.temp, nullptr, st);
+  // 3. entries, then a stable sort by (view, tile)
+  const int bits = key_bits_for((int64_t)a.V * tiles);
+  const int passes = (bits + 7) / 8;
+  uint32_t* K[2] = {w.ek[0], a.keys ? a.keys : w.ek[1]};
+  uint32_t* Vv[2] = {w.ev, a.vals};
+  const int start = (passes & 1) ? 0 : 1;
+  k_dup<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), w.cnt, m,
+                                 a.n_max, a.tiles_x, tiles, a.n_entries, K[start], Vv[start]);
+  const int ecur = radix_sort_pairs(K, Vv, start, a.n_entries, passes * 8, w.temp, st);
+  // 4. per-tile ranges
+  k_zero_words<<<nblk(nranges), 256, 0, st>>>(a.ranges, nranges);
+  if (a.n_entries > 0)
+    k_ranges<<<nblk(a.n_entries), 256, 0, st>>>(K[ecur], a.n_entries, (uint32_t)(a.V * tiles), a.ranges);
+}
+
+}  // namespace hyrf

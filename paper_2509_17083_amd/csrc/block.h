@@ -1,0 +1,54 @@
+// Wave64 / workgroup prefix-sum primitives for gfx950.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hyrf {
+
+constexpr int WAVE = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Inclusive prefix sum across the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    uint32_t o = __shfl_up(v, off, WAVE);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ float wave_sum_f32(float v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64,
+// at most 1024).  `sh` must hold NT/64 + 1 uint32.  Returns the exclusive
+// prefix of the calling thread; *total receives the workgroup sum.  Contains
+// __syncthreads(): every thread of the workgroup must call it.
+template <int NT>
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* sh, uint32_t* total) {
+  constexpr int NW = NT / WAVE;
+  const int lane = lane_id();
+  const int w = threadIdx.x / WAVE;
+  uint32_t inc = wave_incl_scan(v);
+  if (lane == WAVE - 1) sh[w] = inc;
+  __syncthreads();
+  if (w == 0) {
+    uint32_t s = lane < NW ? sh[lane] : 0u;
+    uint32_t si = wave_incl_scan(s);
+    if (lane < NW) sh[lane] = si - s;
+    if (lane == NW - 1) sh[NW] = si;
+  }
+  __syncthreads();
+  uint32_t res = sh[w] + inc - v;
+  *total = sh[NW];
+  __syncthreads();
+  return res;
+}
+
+}  // namespace hyrf

@@ -1,0 +1,207 @@
+// Field query building blocks shared by the forward and backward kernels:
+// hash-grid gather for a lane's share of the levels and the tiny MLPs on
+// MFMA (v_mfma_f32_16x16x4_f32).
+//
+// Work unit: one wave evaluates 16 points.  Lane l serves point j = l & 15
+// and lane group g = l >> 4 (0..3).  Group g gathers the levels g, g+4, g+8,
+// g+12, so a point's 2L features are spread over its 4 lanes (L/2 each).
+//
+// The MLPs run transposed, D[out x points] = W[out x in] * X^T[in x points]:
+// the B operand of v_mfma_f32_16x16x4_f32 at lane l is element
+// (k = l>>4, column = l&15), so each lane feeds one of ITS OWN inputs per
+// k-step, and the accumulator lands as (row = 4(l>>4)+r, column = l&15) --
+// again in the lane that owns the point.  A layer's output therefore feeds
+// the next layer's B operand straight from registers; the weights (A
+// operand) are stored pre-permuted in LDS in the matching k order:
+//   input from features:  k-step s of group g = feature 2(g + 4(s>>1)) + (s&1)
+//   input from PE:        k-step L/2 + m of group g = PE value 6g + m
+//   input from a hidden layer: k-step s = 4b + r of group g = unit 16b + 4g + r.
+#pragma once
+#include "internal.h"
+
+namespace hyrf {
+
+constexpr int pad4(int x) { return (x + 3) & ~3; }
+
+template <int L_, int HID_, int NH_>
+struct Shape {
+  static constexpr int L = L_, HID = HID_, NH = NH_;
+  static constexpr int NT = HID / 16;          // 16-row output tiles of a hidden layer
+  static constexpr int LPG = L / 4;            // levels per lane group
+  static constexpr int FPL = L / 2;            // features per lane (per field)
+  static constexpr int S_GEO1 = pad4(L / 2);
+  static constexpr int S_COL1 = pad4(L / 2 + 6);
+  static constexpr int S_HID = HID / 4;
+  static constexpr int IN_GEO = 2 * L;
+  static constexpr int IN_COL = 2 * L + 6 * HYRF_PE_OCTAVES;
+  // LDS floats per MLP
+  static constexpr int W_GEO = NT * S_GEO1 * 64 + (NH - 1) * NT * S_HID * 64 + S_HID * 64;
+  static constexpr int W_COL = NT * S_COL1 * 64 + (NH - 1) * NT * S_HID * 64 + S_HID * 64;
+  // flat float32 weight counts
+  static constexpr int N_GEO = HID * IN_GEO + (NH - 1) * HID * HID + HYRF_GEO_OUT * HID;
+  static constexpr int N_COL = HID * IN_COL + (NH - 1) * HID * HID + HYRF_COL_OUT * HID;
+};
+
+// k index (input column) fed by lane group g at k-step s of a first layer.
+template <int L>
+__device__ __forceinline__ int first_layer_col(int s, int g, bool colour) {
+  if (s < L / 2) return 2 * (g + 4 * (s >> 1)) + (s & 1);
+  if (colour && s < L / 2 + 6) return 2 * L + 6 * g + (s - L / 2);
+  return -1;
+}
+
+// Fill LDS with one MLP's weights in the permuted A-operand order.
+// Layout per layer: [out_tile][s/4][lane][s%4].
+template <class Sh>
+__device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colour) {
+  const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
+  const int in1 = colour ? Sh::IN_COL : Sh::IN_GEO;
+  const int S1 = colour ? Sh::S_COL1 : Sh::S_GEO1;
+  // layer table: (lds offset, global offset, S, out tiles, rows, in, kind)
+  int lds_off = 0, g_off = 0;
+  for (int layer = 0; layer <= Sh::NH; ++layer) {
+    const bool first = layer == 0;
+    const bool last = layer == Sh::NH;
+    const int S = first ? S1 : Sh::S_HID;
+    const int NTo = last ? 1 : Sh::NT;
+    const int rows = last ? n_out : Sh::HID;
+    const int in = first ? in1 : Sh::HID;
+    const int cnt = NTo * S * 64;
+    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const int s4 = e & 3;
+      const int lane = (e >> 2) & 63;
+      const int rest = e >> 8;                 // ot * (S/4) + sq
+      const int sq = rest % (S / 4);
+      const int ot = rest / (S / 4);
+      const int s = sq * 4 + s4;
+      const int g = lane >> 4;
+      const int row = ot * 16 + (lane & 15);
+      int col = first ? first_layer_col<Sh::L>(s, g, colour) : (16 * sq + 4 * g + s4);
+      float val = 0.f;
+      if (row < rows && col >= 0 && col < in) val = W[g_off + row * in + col];
+      lds[lds_off + e] = val;
+    }
+    lds_off += cnt;
+    g_off += rows * in;
+  }
+}
+
+// One layer: acc[ot] = sum_s W(ot, s) * x[s]   (x: this lane's B operands).
+template <int NTO, int S>
+__device__ __forceinline__ void mfma_layer(const float* __restrict__ Wl, const float (&x)[S],
+                                           v4f (&acc)[NTO], int lane) {
+#pragma unroll
+  for (int ot = 0; ot < NTO; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int sq = 0; sq < S / 4; ++sq) {
+#pragma unroll
+    for (int ot = 0; ot < NTO; ++ot) {
+      const float4 w = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq) * 64 + lane) * 4);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, x[4 * sq + 0], acc[ot], 0, 0, 0);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, x[4 * sq + 1], acc[ot], 0, 0, 0);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, x[4 * sq + 2], acc[ot], 0, 0, 0);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, x[4 * sq + 3], acc[ot], 0, 0, 0);
+    }
+    // keep the weight reads of one k-quad in flight at a time (register budget)
+    asm volatile("" ::: "memory");
+  }
+}
+
+template <int NTO>
+__device__ __forceinline__ void relu_to_inputs(const v4f (&acc)[NTO], float (&x)[NTO * 4]) {
+#pragma unroll
+  for (int b = 0; b < NTO; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[4 * b + r] = fmaxf(acc[b][r], 0.f);
+}
+
+// Whole MLP from first-layer inputs x1 to the 16-row output tile `out`
+// (lane holds rows 4g..4g+3).  Optionally keeps the hidden activations
+// (pre-ReLU) for the backward.
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward(const float* __restrict__ Wlds, const float (&x1)[S1],
+                                            v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer<Sh::NT, S1>(Wlds, x1, acc, lane);
+  const float* W = Wlds + Sh::NT * S1 * 64;
+  float h[Sh::S_HID];
+  relu_to_inputs<Sh::NT>(acc, h);
+#pragma unroll
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer<Sh::NT, Sh::S_HID>(W, h, acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(acc, h);
+  }
+  v4f o[1];
+  mfma_layer<1, Sh::S_HID>(W, h, o, lane);
+  out = o[0];
+}
+
+// Gather this lane's levels from both tables at contracted position x.
+// fg / fr: lane features (level g + 4k, feature f) at index 2k + f.
+template <int L, bool GEO>
+__device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], int g,
+                                            const float* __restrict__ tg, const float* __restrict__ tr,
+                                            float (&fg)[L / 2], float (&fr)[L / 2],
+                                            uint32_t* dbg_geo, uint32_t* dbg_rad) {
+  const uint32_t Tg = gp.mask_geo + 1u, Tr = gp.mask_rad + 1u;
+#pragma unroll
+  for (int k = 0; k < L / 4; ++k) {
+    const int lev = g + 4 * k;
+    const int res = gp.res[lev];
+    int ci[3];
+    float w[3];
+    grid_cell(x, res, ci, w);
+    const uint32_t side = (uint32_t)res + 1u;
+    const bool dg = (gp.dense_geo >> lev) & 1u;
+    const bool dr = (gp.dense_rad >> lev) & 1u;
+    float2 vg[8], vr[8];
+    float wc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t cx = (uint32_t)ci[0] + (c & 1);
+      const uint32_t cy = (uint32_t)ci[1] + ((c >> 1) & 1);
+      const uint32_t cz = (uint32_t)ci[2] + ((c >> 2) & 1);
+      const float wx = (c & 1) ? w[0] : 1.f - w[0];
+      const float wy = ((c >> 1) & 1) ? w[1] : 1.f - w[1];
+      const float wz = ((c >> 2) & 1) ? w[2] : 1.f - w[2];
+      wc[c] = (wx * wy) * wz;
+      const uint32_t rr = corner_row(cx, cy, cz, dr, side, gp.mask_rad);
+      vr[c] = *reinterpret_cast<const float2*>(tr + ((size_t)lev * Tr + rr) * 2);
+      if (dbg_rad) dbg_rad[lev * 8 + c] = rr;
+      if (GEO) {
+        const uint32_t rg = corner_row(cx, cy, cz, dg, side, gp.mask_geo);
+        vg[c] = *reinterpret_cast<const float2*>(tg + ((size_t)lev * Tg + rg) * 2);
+        if (dbg_geo) dbg_geo[lev * 8 + c] = rg;
+      }
+    }
+    float a0 = 0.f, a1 = 0.f, b0 = 0.f, b1 = 0.f;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      a0 = fmaf(wc[c], vr[c].x, a0);
+      a1 = fmaf(wc[c], vr[c].y, a1);
+      if (GEO) {
+        b0 = fmaf(wc[c], vg[c].x, b0);
+        b1 = fmaf(wc[c], vg[c].y, b1);
+      }
+    }
+    fr[2 * k] = a0;
+    fr[2 * k + 1] = a1;
+    if (GEO) {
+      fg[2 * k] = b0;
+      fg[2 * k + 1] = b1;
+    }
+    // one level's 16 loads in flight per lane at a time (register budget)
+    asm volatile("" ::: "memory");
+  }
+}
+
+// PE values of lane group g (octave g): sin(2^g pi d) then cos(2^g pi d).
+__device__ __forceinline__ void pe_lane(int g, float dx, float dy, float dz, float pe[6]) {
+  const float sc = (float)(1 << g);
+  sincospif(sc * dx, &pe[0], &pe[3]);
+  sincospif(sc * dy, &pe[1], &pe[4]);
+  sincospif(sc * dz, &pe[2], &pe[5]);
+}
+
+}  // namespace hyrf

@@ -1,0 +1,44 @@
+// Host-side launch helpers shared between the kernel translation units and
+// the C ABI (internal; not exported).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "internal.h"
+
+namespace hyrf {
+
+// Carves 256-byte aligned chunks out of a caller workspace; with base == NULL
+// it only measures.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(void* b) : base((char*)b) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? (T*)(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ---- scan.hip
+constexpr int SCAN_ITEMS = 4096;   // items per workgroup
+size_t scan_temp_elems(int64_t n);
+// Exclusive prefix sum of n uint32 values (in may equal out); temp holds
+// scan_temp_elems(n) uint32; total (device, may be NULL) receives the sum.
+void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp,
+                        uint32_t* total, hipStream_t s);
+
+// ---- sort.hip
+constexpr int SORT_ITEMS = 4096;   // items per workgroup and pass
+size_t radix_temp_elems(int64_t n);
+// Stable LSD radix sort of (key, value) pairs by key bits [0, bits), 8 bits
+// per pass, ping-ponging between (k[0], v[0]) and (k[1], v[1]); the input is
+// in slot `start`; returns the slot that holds the result.
+int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
+                     uint32_t* temp, hipStream_t s);
+
+}  // namespace hyrf

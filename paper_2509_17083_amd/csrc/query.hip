@@ -1,0 +1,218 @@
+// Pre-cull + compaction, field query of the survivors, and the background
+// query of pixel rays (Sec. 3.2 Eqs. 2-7, Sec. 3.3).
+#include "block.h"
+#include "field.h"
+#include "kernels.h"
+#include "query.h"
+
+namespace hyrf {
+
+// ---------------------------------------------------------------- pre-cull
+__global__ __launch_bounds__(256) void k_cull_flags(const float* __restrict__ pos, int n, Cams cams,
+                                                    uint32_t* __restrict__ flag) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double px = pos[i], py = pos[n + i], pz = pos[2 * n + i];
+  bool keep = false;
+  for (int v = 0; v < cams.V; ++v) {
+    double t[3];
+    cam_space_f64(cams.c[v], px, py, pz, t);
+    keep |= precull_f64(cams.c[v], t);
+  }
+  flag[i] = keep ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(256) void k_cull_write(const uint32_t* __restrict__ flag,
+                                                    const uint32_t* __restrict__ pos_, int n,
+                                                    int32_t* __restrict__ vis_idx) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (flag[i]) vis_idx[pos_[i]] = i;
+}
+
+// ---------------------------------------------------------------- field query
+template <class Sh>
+__global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
+  __shared__ __attribute__((aligned(16))) float w_geo[Sh::W_GEO];
+  __shared__ __attribute__((aligned(16))) float w_col[Sh::W_COL];
+  load_mlp_lds<Sh>(w_geo, a.w_geo, false);
+  load_mlp_lds<Sh>(w_col, a.w_col, true);
+  __syncthreads();
+
+  const int lane = lane_id();
+  const int j = lane & 15, g = lane >> 4;
+  const int count = *a.count;
+  const int groups = (count + 15) >> 4;
+  const int wave_g = blockIdx.x * (QUERY_NT / 64) + threadIdx.x / 64;
+  const int wave_n = gridDim.x * (QUERY_NT / 64);
+  const int n = a.n;
+
+  for (int grp = wave_g; grp < groups; grp += wave_n) {
+    const int slot = grp * 16 + j;
+    const bool valid = slot < count;
+    const int gi = valid ? a.vis_idx[slot] : a.vis_idx[0];
+    const float pxf = a.pos[gi], pyf = a.pos[n + gi], pzf = a.pos[2 * n + gi];
+    double x[3];
+    contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
+    float fg[Sh::FPL], fr[Sh::FPL];
+    uint32_t* dg = nullptr;
+    uint32_t* dr = nullptr;
+    if (a.dbg && valid) {
+      dg = a.dbg + (size_t)slot * 2 * Sh::L * 8;
+      dr = dg + Sh::L * 8;
+    }
+    gather_lane<Sh::L, true>(a.grid, x, g, a.table_geo, a.table_rad, fg, fr, dg, dr);
+    if (a.feat_geo && valid) {
+#pragma unroll
+      for (int k = 0; k < Sh::L / 4; ++k) {
+        const int lev = g + 4 * k;
+        *reinterpret_cast<float2*>(a.feat_geo + (size_t)slot * 2 * Sh::L + 2 * lev) = make_float2(fg[2 * k], fg[2 * k + 1]);
+        *reinterpret_cast<float2*>(a.feat_rad + (size_t)slot * 2 * Sh::L + 2 * lev) = make_float2(fr[2 * k], fr[2 * k + 1]);
+      }
+    }
+    // geometry decoder
+    float xg[Sh::S_GEO1];
+#pragma unroll
+    for (int s = 0; s < Sh::S_GEO1; ++s) xg[s] = s < Sh::FPL ? fg[s] : 0.f;
+    v4f og;
+    mlp_forward<Sh, Sh::S_GEO1>(w_geo, xg, og, lane);
+    // rows 4..7 (rotation) live in lane group 1: bring them to group 0
+    float rn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rn[r] = __shfl(og[r], j + 16, 64);
+    if (g == 0 && valid) {
+      const float op = sigmoidf_(og[0] + a.opac_e[gi]);
+      a.opacity[slot] = op;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) a.scale[(size_t)d * n + slot] = sigmoidf_(og[1 + d] + a.scale_e[(size_t)d * n + gi]);
+      float q[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) q[r] = rn[r] + (a.rot_e ? a.rot_e[(size_t)r * n + gi] : 0.f);
+      const float inv = 1.0f / sqrtf((q[0] * q[0] + q[1] * q[1]) + (q[2] * q[2] + q[3] * q[3]));
+#pragma unroll
+      for (int r = 0; r < 4; ++r) a.quat[(size_t)r * n + slot] = q[r] * inv;
+    }
+    // colour decoder, once per view
+    for (int v = 0; v < a.cams.V; ++v) {
+      float oc[3];
+      cam_center_f32(a.cams.c[v], oc);
+      float dx = pxf - oc[0], dy = pyf - oc[1], dz = pzf - oc[2];
+      const float inv = 1.0f / sqrtf((dx * dx + dy * dy) + dz * dz);
+      dx *= inv; dy *= inv; dz *= inv;
+      float pe[6];
+      pe_lane(g, dx, dy, dz, pe);
+      float xc[Sh::S_COL1];
+#pragma unroll
+      for (int s = 0; s < Sh::S_COL1; ++s)
+        xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
+      v4f oc4;
+      mlp_forward<Sh, Sh::S_COL1>(w_col, xc, oc4, lane);
+      if (g == 0 && valid) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+          a.rgb[((size_t)v * 3 + c) * n + slot] = sigmoidf_(oc4[c] + a.col_e[(size_t)c * n + gi]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- background
+template <class Sh>
+__global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
+  __shared__ __attribute__((aligned(16))) float w_col[Sh::W_COL];
+  load_mlp_lds<Sh>(w_col, a.w_col, true);
+  __syncthreads();
+  const int lane = lane_id();
+  const int j = lane & 15, g = lane >> 4;
+  const int HW = a.W * a.H;
+  const int count = a.list_count ? *a.list_count : a.cams.V * HW;
+  const int groups = (count + 15) >> 4;
+  const int wave_g = blockIdx.x * (QUERY_NT / 64) + threadIdx.x / 64;
+  const int wave_n = gridDim.x * (QUERY_NT / 64);
+  const double radius = (double)a.grid.bg_radius;
+  for (int grp = wave_g; grp < groups; grp += wave_n) {
+    const int item = grp * 16 + j;
+    const bool valid = item < count;
+    const int pix = valid ? (a.list ? (int)a.list[item] : item) : 0;
+    const int v = pix / HW;
+    const int rem = pix - v * HW;
+    const int y = rem / a.W, xq = rem - y * a.W;
+    double ps[3], d[3];
+    sphere_point_f64(a.cams.c[v], xq, y, radius, ps, d);
+    double x[3];
+    contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+    float fg[Sh::FPL], fr[Sh::FPL];
+    gather_lane<Sh::L, false>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
+    const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+    float pe[6];
+    pe_lane(g, (float)(d[0] / dn), (float)(d[1] / dn), (float)(d[2] / dn), pe);
+    float xc[Sh::S_COL1];
+#pragma unroll
+    for (int s = 0; s < Sh::S_COL1; ++s)
+      xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
+    v4f o;
+    mlp_forward<Sh, Sh::S_COL1>(w_col, xc, o, lane);
+    if (g == 0 && valid) {
+      const float T = a.T[pix];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float cs = sigmoidf_(o[c]);
+        const size_t at = ((size_t)v * 3 + c) * HW + rem;
+        a.out_rgb[at] = fmaf(T, cs, a.out_rgb[at]);
+        if (a.bg_save) a.bg_save[at] = cs;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+template <class Sh>
+static void launch_query_t(const QueryArgs& a, int n_cap, hipStream_t st) {
+  int groups = (n_cap + 15) / 16;
+  int blocks = (groups + QUERY_NT / 64 - 1) / (QUERY_NT / 64);
+  if (blocks > QUERY_MAX_BLOCKS) blocks = QUERY_MAX_BLOCKS;
+  if (blocks < 1) blocks = 1;
+  k_field_query<Sh><<<blocks, QUERY_NT, 0, st>>>(a);
+}
+
+template <class Sh>
+static void launch_bg_t(const BgArgs& a, int n_cap, hipStream_t st) {
+  int groups = (n_cap + 15) / 16;
+  int blocks = (groups + QUERY_NT / 64 - 1) / (QUERY_NT / 64);
+  if (blocks > QUERY_MAX_BLOCKS) blocks = QUERY_MAX_BLOCKS;
+  if (blocks < 1) blocks = 1;
+  k_bg_query<Sh><<<blocks, QUERY_NT, 0, st>>>(a);
+}
+
+bool shape_supported(int L, int hid, int nh) {
+  return (L == 16 && hid == 64 && nh == 2) || (L == 8 && hid == 32 && nh == 1) ||
+         (L == 16 && hid == 64 && nh == 1) || (L == 8 && hid == 64 && nh == 2);
+}
+
+#define HYRF_SHAPES(X) X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
+
+void launch_query(int L, int hid, int nh, const QueryArgs& a, int n_cap, hipStream_t st) {
+#define X(l, h, k) if (L == l && hid == h && nh == k) return launch_query_t<Shape<l, h, k>>(a, n_cap, st);
+  HYRF_SHAPES(X)
+#undef X
+}
+
+void launch_bg(int L, int hid, int nh, const BgArgs& a, int n_cap, hipStream_t st) {
+#define X(l, h, k) if (L == l && hid == h && nh == k) return launch_bg_t<Shape<l, h, k>>(a, n_cap, st);
+  HYRF_SHAPES(X)
+#undef X
+}
+
+void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
+                 uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st) {
+  if (n <= 0) {
+    scan_exclusive_u32(nullptr, nullptr, 0, scan_temp, (uint32_t*)vis_count, st);
+    return;
+  }
+  const int nb = (n + 255) / 256;
+  k_cull_flags<<<nb, 256, 0, st>>>(pos, n, cams, flag);
+  scan_exclusive_u32(flag, pos_, n, scan_temp, (uint32_t*)vis_count, st);
+  k_cull_write<<<nb, 256, 0, st>>>(flag, pos_, n, vis_idx);
+}
+
+}  // namespace hyrf

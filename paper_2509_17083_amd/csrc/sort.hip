@@ -1,0 +1,120 @@
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
+// reduce-then-scan per pass (no inter-workgroup waiting):
+//   1. per-workgroup digit histogram -> hist[digit * nblocks + block]
+//   2. exclusive scan of hist (digit-major) -> global base of (digit, block)
+//   3. per-workgroup stable ranking and scatter.
+// Each workgroup owns SORT_ITEMS consecutive pairs; wave w owns the w-th
+// quarter and walks it in 64-item rounds, so the rank of an item among equal
+// digits follows input order (stability).
+#include "block.h"
+#include "kernels.h"
+
+namespace hyrf {
+
+namespace {
+constexpr int NT = 256;
+constexpr int NW = NT / WAVE;                 // 4 waves
+constexpr int ROUNDS = SORT_ITEMS / NT;       // 16 rounds of 64 per wave
+constexpr int RADIX = 256;
+
+__global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
+                                                   int shift, uint32_t* __restrict__ hist,
+                                                   int nblocks) {
+  __shared__ uint32_t h[RADIX];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+#pragma unroll 4
+  for (int r = 0; r < ROUNDS; ++r) {
+    int64_t i = base + (int64_t)r * NT + threadIdx.x;
+    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict__ kin,
+                                                      const uint32_t* __restrict__ vin,
+                                                      uint32_t* __restrict__ kout,
+                                                      uint32_t* __restrict__ vout, int64_t n,
+                                                      int shift, const uint32_t* __restrict__ hist,
+                                                      int nblocks) {
+  __shared__ uint32_t cnt[NW][RADIX];
+  const int lane = lane_id();
+  const int w = threadIdx.x / WAVE;
+  for (int k = threadIdx.x; k < NW * RADIX; k += NT) (&cnt[0][0])[k] = 0;
+  __syncthreads();
+
+  const int64_t chunk = (int64_t)blockIdx.x * SORT_ITEMS + (int64_t)w * (ROUNDS * WAVE);
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int64_t i = chunk + (int64_t)r * WAVE + lane;
+    const bool ok = i < n;
+    uint32_t k = ok ? kin[i] : 0u;
+    key[r] = k;
+    val[r] = ok ? vin[i] : 0u;
+    const uint32_t d = (k >> shift) & 0xFFu;
+    // lanes holding the same digit (out-of-range lanes form their own group)
+    uint64_t m = __ballot(ok);
+    if (!ok) m = ~m;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      uint64_t bb = __ballot((d >> b) & 1u);
+      m &= ((d >> b) & 1u) ? bb : ~bb;
+    }
+    uint32_t before = ok ? cnt[w][d] : 0u;
+    rank[r] = before + (uint32_t)__popcll(m & lt);
+    const bool leader = (m >> lane) == 1ull;     // highest lane of its group
+    if (ok && leader) cnt[w][d] = before + (uint32_t)__popcll(m);
+  }
+  __syncthreads();
+  // per digit: prefix over waves + global base of (digit, block)
+  {
+    const int d = threadIdx.x;
+    uint32_t run = hist[(int64_t)d * nblocks + blockIdx.x];
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) {
+      uint32_t c = cnt[ww][d];
+      cnt[ww][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r) {
+    const int64_t i = chunk + (int64_t)r * WAVE + lane;
+    if (i < n) {
+      const uint32_t d = (key[r] >> shift) & 0xFFu;
+      const uint32_t pos = cnt[w][d] + rank[r];
+      kout[pos] = key[r];
+      vout[pos] = val[r];
+    }
+  }
+}
+}  // namespace
+
+size_t radix_temp_elems(int64_t n) {
+  int64_t nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+  if (nb < 1) nb = 1;
+  return (size_t)nb * RADIX + scan_temp_elems(nb * RADIX);
+}
+
+int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
+                     uint32_t* temp, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return start;
+  const int nb = (int)((n + SORT_ITEMS - 1) / SORT_ITEMS);
+  uint32_t* hist = temp;
+  uint32_t* stemp = temp + (size_t)nb * RADIX;
+  int cur = start;
+  for (int shift = 0; shift < bits; shift += 8) {
+    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, shift, hist, nb);
+    scan_exclusive_u32(hist, hist, (int64_t)nb * RADIX, stemp, nullptr, st);
+    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, hist, nb);
+    cur ^= 1;
+  }
+  return cur;
+}
+
+}  // namespace hyrf

@@ -1,0 +1,248 @@
+"""Python binding of the HyRF render step: device buffers (torch tensors,
+used only for device memory and streams) and the calls of the C ABI in
+their order.  Every step of the computation runs in libhyrf.so.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi as A
+
+F32, F16, BF16 = A.HYRF_F32, A.HYRF_F16, A.HYRF_BF16
+RENDER, TRAIN = A.HYRF_RENDER, A.HYRF_TRAIN
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+@dataclass
+class DeviceScene:
+    """Explicit Gaussians + both fields resident on the GPU (planar float32)."""
+    pos: torch.Tensor          # (3, n)
+    scale_e: torch.Tensor      # (3, n)
+    rot_e: Optional[torch.Tensor]  # (4, n) or None
+    opac_e: torch.Tensor       # (n,)
+    col_e: torch.Tensor        # (3, n)
+    table_geo: torch.Tensor    # (L, T_geo, 2)
+    table_rad: torch.Tensor    # (L, T_rad, 2)
+    mlp_geo: torch.Tensor      # flat float32
+    mlp_col: torch.Tensor
+    levels: int
+    log2_T_geo: int
+    log2_T_rad: int
+    hidden: int
+    n_hidden: int
+    base_res: float = 16.0
+    growth: float = 1.5
+    aabb_center: Sequence[float] = (0.0, 0.0, 0.0)
+    aabb_inv_half: Sequence[float] = (1.0, 1.0, 1.0)
+    bg_radius: float = 100.0
+    tau_T: float = 0.2
+    table_dtype: int = F32
+    mlp_dtype: int = F32
+
+    @property
+    def n(self) -> int:
+        return int(self.pos.shape[1])
+
+    @staticmethod
+    def from_host(s, device: str = "cuda") -> "DeviceScene":
+        """From an object with numpy fields pos (3,n), scale_e, rot_e, opac_e,
+        col_e, table_geo, table_rad, mlp_geo / mlp_col (lists of [out][in])
+        and a cfg with levels, log2_T_rad, log2_T_geo, hidden, n_hidden,
+        base_res, growth."""
+        def t(a):
+            return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(device)
+        cfg = s.cfg
+        return DeviceScene(
+            pos=t(s.pos), scale_e=t(s.scale_e), rot_e=None if s.rot_e is None else t(s.rot_e),
+            opac_e=t(s.opac_e), col_e=t(s.col_e), table_geo=t(s.table_geo), table_rad=t(s.table_rad),
+            mlp_geo=t(np.concatenate([w.reshape(-1) for w in s.mlp_geo])),
+            mlp_col=t(np.concatenate([w.reshape(-1) for w in s.mlp_col])),
+            levels=cfg.levels, log2_T_geo=cfg.log2_T_geo, log2_T_rad=cfg.log2_T_rad,
+            hidden=cfg.hidden, n_hidden=cfg.n_hidden, base_res=cfg.base_res, growth=cfg.growth,
+            aabb_center=tuple(float(x) for x in s.aabb_center),
+            aabb_inv_half=tuple(float(x) for x in s.aabb_inv_half),
+            bg_radius=float(s.bg_radius), tau_T=float(s.tau_T))
+
+    def c_fields(self) -> A.hyrf_fields:
+        f = A.hyrf_fields()
+        f.levels, f.features = self.levels, 2
+        f.log2_T_geo, f.log2_T_rad = self.log2_T_geo, self.log2_T_rad
+        f.base_res, f.growth = self.base_res, self.growth
+        f.table_dtype = self.table_dtype
+        f.table_geo, f.table_rad = self.table_geo.data_ptr(), self.table_rad.data_ptr()
+        f.hidden, f.n_hidden, f.mlp_dtype = self.hidden, self.n_hidden, self.mlp_dtype
+        f.mlp_geo, f.mlp_col = self.mlp_geo.data_ptr(), self.mlp_col.data_ptr()
+        f.aabb_center[:] = list(self.aabb_center)
+        f.aabb_inv_half[:] = list(self.aabb_inv_half)
+        f.bg_radius, f.tau_T = self.bg_radius, self.tau_T
+        return f
+
+    def c_gauss(self) -> A.hyrf_gaussians:
+        g = A.hyrf_gaussians()
+        g.n = self.n
+        g.pos, g.scale_e, g.opac_e, g.col_e = (self.pos.data_ptr(), self.scale_e.data_ptr(),
+                                               self.opac_e.data_ptr(), self.col_e.data_ptr())
+        g.rot_e = None if self.rot_e is None else self.rot_e.data_ptr()
+        return g
+
+
+def c_cameras(cams) -> "C.Array":
+    arr = (A.hyrf_camera * len(cams))()
+    for k, c in enumerate(cams):
+        arr[k].R[:] = [float(x) for x in np.asarray(c.R, np.float32).reshape(-1)]
+        arr[k].t[:] = [float(x) for x in np.asarray(c.t, np.float32).reshape(-1)]
+        arr[k].fx, arr[k].fy, arr[k].cx, arr[k].cy = c.fx, c.fy, c.cx, c.cy
+        arr[k].width, arr[k].height = c.width, c.height
+        arr[k].z_near, arr[k].cull_tol = c.z_near, c.cull_tol
+    return arr
+
+
+class Workspace:
+    """Grow-only device scratch buffers, one per named use."""
+
+    def __init__(self):
+        self.bufs: Dict[str, torch.Tensor] = {}
+
+    def get(self, name: str, nbytes: int) -> torch.Tensor:
+        b = self.bufs.get(name)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
+            self.bufs[name] = b
+        return b
+
+
+@dataclass
+class ForwardState:
+    mode: int
+    V: int
+    W: int
+    H: int
+    n_entries: int
+    query: Dict[str, torch.Tensor]
+    splats: Dict[str, torch.Tensor]
+    vals: torch.Tensor
+    keys: Optional[torch.Tensor]
+    ranges: torch.Tensor
+    image: torch.Tensor     # (V, 3, H, W)
+    T: torch.Tensor         # (V, H, W)
+    last: Optional[torch.Tensor]
+    bg: Optional[torch.Tensor]
+    c: Dict[str, object] = field(default_factory=dict)   # ctypes structs kept alive
+
+
+def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False,
+                 ws: Optional[Workspace] = None):
+    lib = A.load()
+    ws = ws or Workspace()
+    n, V, L = scene.n, len(cams), scene.levels
+    dev = scene.pos.device
+    q = dict(vis_count=torch.zeros(1, dtype=torch.int32, device=dev),
+             vis_idx=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
+             opacity=torch.empty(max(n, 1), device=dev), scale=torch.empty(3, max(n, 1), device=dev),
+             quat=torch.empty(4, max(n, 1), device=dev), rgb=torch.empty(V, 3, max(n, 1), device=dev))
+    if mode == TRAIN:
+        q["feat_geo"] = torch.empty(max(n, 1), 2 * L, device=dev)
+        q["feat_rad"] = torch.empty(max(n, 1), 2 * L, device=dev)
+    if debug_index:
+        q["dbg_index"] = torch.empty(max(n, 1), 2, L, 8, dtype=torch.int32, device=dev)
+    out = A.hyrf_query_out(*[q[k].data_ptr() if k in q else None for k in
+                             ("vis_count", "vis_idx", "opacity", "scale", "quat", "rgb", "feat_geo",
+                              "feat_rad", "dbg_index")])
+    f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
+    nb = lib.hyrf_query_workspace_bytes(n)
+    w = ws.get("query", nb)
+    A.check("hyrf_query_fields", lib.hyrf_query_fields(C.byref(f), C.byref(g), cc, V, C.byref(out),
+                                                       _p(w), w.numel(), _stream()))
+    return q, out
+
+
+def project(scene: DeviceScene, cams, q, qout):
+    lib = A.load()
+    n, V = scene.n, len(cams)
+    dev = scene.pos.device
+    sp = dict(rec=torch.empty(V, max(n, 1), 12, device=dev),
+              rect=torch.empty(V, max(n, 1), 4, dtype=torch.int32, device=dev),
+              depth=torch.empty(V, max(n, 1), device=dev),
+              total=torch.zeros(1, dtype=torch.int64, device=dev))
+    cs = A.hyrf_splats(max(n, 1), q["vis_count"].data_ptr(), sp["rec"].data_ptr(), sp["rect"].data_ptr(),
+                       sp["depth"].data_ptr(), sp["total"].data_ptr())
+    g, cc = scene.c_gauss(), c_cameras(cams)
+    A.check("hyrf_project", lib.hyrf_project(C.byref(g), C.byref(qout), cc, V, C.byref(cs), _stream()))
+    return sp, cs
+
+
+def bin_sort(cams, splats_c, n_max: int, n_entries: int, want_keys: bool = False,
+             ws: Optional[Workspace] = None, capacity: Optional[int] = None):
+    lib = A.load()
+    ws = ws or Workspace()
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    tiles = ((W + 15) // 16) * ((H + 15) // 16)
+    cap = n_entries if capacity is None else capacity
+    vals = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda")
+    keys = torch.empty(max(cap, 1), dtype=torch.int32, device="cuda") if want_keys else None
+    ranges = torch.empty(V * tiles, 2, dtype=torch.int32, device="cuda")
+    nb = lib.hyrf_bin_sort_workspace_bytes(V, n_max, cap, W, H)
+    w = ws.get("bin", nb)
+    cc = c_cameras(cams)
+    A.check("hyrf_bin_sort", lib.hyrf_bin_sort(C.byref(splats_c), cc, V, n_entries, cap, _p(keys), _p(vals),
+                                               _p(ranges), _p(w), w.numel(), _stream()))
+    return keys, vals, ranges
+
+
+def composite(scene: Optional[DeviceScene], cams, splats_c, vals, ranges, mode: int,
+              ws: Optional[Workspace] = None):
+    lib = A.load()
+    ws = ws or Workspace()
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    img = torch.empty(V, 3, H, W, device="cuda")
+    T = torch.empty(V, H, W, device="cuda")
+    last = torch.empty(V, H, W, dtype=torch.int32, device="cuda") if mode == TRAIN else None
+    bg = torch.empty(V, 3, H, W, device="cuda") if (mode == TRAIN and scene is not None) else None
+    nb = lib.hyrf_composite_workspace_bytes(V, W, H)
+    w = ws.get("composite", nb)
+    cc = c_cameras(cams)
+    f = scene.c_fields() if scene is not None else None
+    A.check("hyrf_composite", lib.hyrf_composite(C.byref(splats_c), _p(vals), _p(ranges), cc, V,
+                                                 C.byref(f) if f is not None else None, mode, _p(img), _p(T),
+                                                 _p(last), _p(bg), _p(w), w.numel(), _stream()))
+    return img, T, last, bg
+
+
+def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False, want_keys: bool = False,
+           ws: Optional[Workspace] = None) -> ForwardState:
+    """The forward render step: query -> project -> bin/sort -> composite
+    (+ background).  One host read (the tile-entry count)."""
+    ws = ws or Workspace()
+    V, W, H = len(cams), cams[0].width, cams[0].height
+    q, qout = query_fields(scene, cams, mode, debug_index, ws)
+    sp, spc = project(scene, cams, q, qout)
+    n_entries = int(sp["total"].item())
+    keys, vals, ranges = bin_sort(cams, spc, max(scene.n, 1), n_entries, want_keys, ws)
+    img, T, last, bg = composite(scene, cams, spc, vals, ranges, mode, ws)
+    return ForwardState(mode=mode, V=V, W=W, H=H, n_entries=n_entries, query=q, splats=sp, vals=vals,
+                        keys=keys, ranges=ranges, image=img, T=T, last=last, bg=bg,
+                        c=dict(qout=qout, splats=spc))
+
+
+def l1_loss(img: torch.Tensor, target: torch.Tensor, grad: bool = True, ws: Optional[Workspace] = None):
+    lib = A.load()
+    ws = ws or Workspace()
+    n = img.numel()
+    loss = torch.empty(1, device="cuda")
+    g = torch.empty_like(img) if grad else None
+    w = ws.get("l1", lib.hyrf_l1_workspace_bytes(n))
+    A.check("hyrf_l1_loss", lib.hyrf_l1_loss(_p(img), _p(target), n, _p(loss), _p(g), _p(w), w.numel(),
+                                             _stream()))
+    return loss, g

@@ -1,0 +1,198 @@
+"""GPU parity of the forward render step against the FP64 oracle, through
+the C ABI.  Integer work (culling, hash indices, binning order) must match
+bit for bit; float32 values within the stated tolerances."""
+import numpy as np
+import pytest
+import torch
+
+import hyrf_inputs as hi
+from oracle import hyrf_oracle as O
+from _hyrf_testutil import compare_image, device_scene, make, oracle_view
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2509_17083_amd as P
+    return P
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _P()._abi.load()
+    _say("device:", torch.cuda.get_device_name(0))
+
+
+# ------------------------------------------------------------------ query
+@pytest.mark.parametrize("cfg_name,over,table_init", [
+    ("tiny", {}, 1.0),
+    ("tiny", {}, None),
+    ("c100k", {"n_gauss": 20000, "width": 320, "height": 240, "focal": 350.0}, 1.0),
+])
+def test_query_indices_and_values(cfg_name, over, table_init):
+    _say("case", cfg_name, over, table_init)
+    P = _P()
+    cfg, scene, cams = make(cfg_name, table_init=table_init, **over)
+    ds = device_scene(scene)
+    q, _ = P.query_fields(ds, cams, P.TRAIN, debug_index=True)
+    torch.cuda.synchronize()
+    params, fields = O.from_scene(scene)
+    keep = O.precull(params.pos, cams[0])
+    idx = torch.nonzero(keep, as_tuple=True)[0]
+    cnt = int(q["vis_count"].item())
+    assert cnt == idx.numel()
+    assert np.array_equal(q["vis_idx"][:cnt].cpu().numpy(), idx.numpy())
+    with torch.no_grad():
+        qo = O.query_gaussians(params, fields, idx, cams[0])
+        x = qo["x"]
+        _, ig = O.hash_encode(x, fields.table_geo, fields.resolutions, return_index=True)
+        _, ir = O.hash_encode(x, fields.table_rad, fields.resolutions, return_index=True)
+    dbg = q["dbg_index"][:cnt].cpu().numpy().astype(np.int64)
+    assert np.array_equal(dbg[:, 0], ig.numpy()), "geometry table rows differ"
+    assert np.array_equal(dbg[:, 1], ir.numpy()), "radiance table rows differ"
+    # features (float32 gather vs float64)
+    fg = q["feat_geo"][:cnt].cpu().double()
+    fr = q["feat_rad"][:cnt].cpu().double()
+    scale_f = max(1.0, float(np.abs(scene.table_rad).max()))
+    assert float((fg - qo["f_geo"]).abs().max()) < 2e-6 * scale_f
+    assert float((fr - qo["f_rad"]).abs().max()) < 2e-6 * scale_f
+    # aggregated properties
+    errs = {
+        "opacity": float((q["opacity"][:cnt].cpu().double() - qo["opacity"]).abs().max()),
+        "scale": float((q["scale"][:, :cnt].cpu().double().T - qo["scale"]).abs().max()),
+        "quat": float((q["quat"][:, :cnt].cpu().double().T - qo["quat"]).abs().max()),
+        "rgb": float((q["rgb"][0, :, :cnt].cpu().double().T - qo["rgb"]).abs().max()),
+    }
+    _say("query errors", errs)
+    for k, e in errs.items():
+        assert e < 2e-5, (k, e)
+
+
+# ------------------------------------------------------------------ projection
+def test_project_matches_oracle():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    ds = device_scene(scene)
+    q, qout = P.query_fields(ds, cams, P.RENDER)
+    sp, spc = P.project(ds, cams, q, qout)
+    torch.cuda.synchronize()
+    r = oracle_view(scene, cams[0], O.RENDER, stats=False)
+    cnt = int(q["vis_count"].item())
+    rec = sp["rec"][0, :cnt].cpu().double()
+    pr = r["proj"]
+    assert np.array_equal(sp["depth"][0, :cnt].cpu().numpy(), r["depth_key"].numpy())
+    live = sp["rect"][0, :cnt].cpu().numpy()
+    live = (live[:, 2] > live[:, 0]) & (live[:, 3] > live[:, 1])
+    uv = torch.stack([pr["u"], pr["v"]], 1)
+    assert float((rec[live, 0:2] - uv[live]).abs().max()) < 1e-3
+    con = pr["conic"]
+    rel = ((rec[live, 2:5] - con[live]).abs() / con[live].abs().amax(1, keepdim=True)).max()
+    assert float(rel) < 1e-4
+    # rectangles hold every pixel the oracle finds with alpha >= 1/255 (brute force)
+    rx, ry = O.splat_extent(pr["cov2d"], r["query"]["opacity"])
+    rect = sp["rect"][0, :cnt].cpu().numpy()
+    W, H = cams[0].width, cams[0].height
+    for i in np.nonzero(live)[0][:200]:
+        xs = np.arange(W) + 0.5
+        ys = np.arange(H) + 0.5
+        dx = float(pr["u"][i]) - xs[None, :]
+        dy = float(pr["v"][i]) - ys[:, None]
+        c = pr["conic"][i].numpy()
+        a = float(r["query"]["opacity"][i]) * np.exp(-0.5 * (c[0] * dx * dx + c[2] * dy * dy) - c[1] * dx * dy)
+        yy, xx = np.nonzero(a >= 1 / 255)
+        if len(xx):
+            assert rect[i, 0] <= xx.min() // 16 and rect[i, 2] > xx.max() // 16
+            assert rect[i, 1] <= yy.min() // 16 and rect[i, 3] > yy.max() // 16
+    tot = int(sp["total"].item())
+    assert tot == int(((rect[:, 2] - rect[:, 0]) * (rect[:, 3] - rect[:, 1]))[live].sum())
+
+
+# ------------------------------------------------------------------ binning / sort
+@pytest.mark.parametrize("V,n,W,H,seed", [(1, 1, 16, 16, 3), (2, 3000, 200, 150, 5), (3, 20000, 1000, 700, 9)])
+def test_bin_sort_bit_exact(V, n, W, H, seed):
+    P = _P()
+    from paper_2509_17083_amd import _abi as A
+    depth, rect, tw, th = hi.make_splat_records(V, n, W, H, seed=seed)
+    keys_o, ids_o, ranges_o = O.bin_and_sort(torch.from_numpy(depth), torch.from_numpy(rect), tw, th)
+    dev = "cuda"
+    d_depth = torch.from_numpy(depth).to(dev)
+    d_rect = torch.from_numpy(rect).to(dev)
+    count = torch.tensor([n], dtype=torch.int32, device=dev)
+    total = torch.zeros(1, dtype=torch.int64, device=dev)
+    spc = A.hyrf_splats(n, count.data_ptr(), None, d_rect.data_ptr(), d_depth.data_ptr(), total.data_ptr())
+    cams = [hi.look_at((0, -3, 0), (0, 0, 0), 100.0, W, H)] * V
+    ne = int(keys_o.numel())
+    keys, vals, ranges = P.bin_sort(cams, spc, n, ne, want_keys=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(vals[:ne].cpu().numpy().astype(np.int64), ids_o.numpy())
+    assert np.array_equal(keys[:ne].cpu().numpy().astype(np.int64), keys_o.numpy())
+    assert np.array_equal(ranges.cpu().numpy().astype(np.int64), ranges_o.numpy())
+
+
+def test_bin_sort_capacity_error():
+    P = _P()
+    from paper_2509_17083_amd import _abi as A
+    depth, rect, tw, th = hi.make_splat_records(1, 100, 64, 64, seed=1)
+    count = torch.tensor([100], dtype=torch.int32, device="cuda")
+    d_rect = torch.from_numpy(rect).cuda()
+    d_depth = torch.from_numpy(depth).cuda()
+    spc = A.hyrf_splats(100, count.data_ptr(), None, d_rect.data_ptr(), d_depth.data_ptr(), None)
+    cams = [hi.look_at((0, -3, 0), (0, 0, 0), 100.0, 64, 64)]
+    with pytest.raises(A.HyrfError) as e:
+        P.bin_sort(cams, spc, 100, 50, capacity=10)
+    assert e.value.status == A.HYRF_ERR_CAPACITY
+
+
+# ------------------------------------------------------------------ whole forward
+@pytest.mark.parametrize("mode", [O.TRAIN, O.RENDER])
+@pytest.mark.parametrize("cfg_name,over,table_init,scale_shift", [
+    ("tiny", {}, None, 0.0),
+    ("tiny", {}, 1.0, 1.0),
+    ("c100k", {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 16}, 1.0, 1.0),
+])
+def test_render_matches_oracle(mode, cfg_name, over, table_init, scale_shift):
+    _say("case", mode, cfg_name, over, table_init, scale_shift)
+    P = _P()
+    cfg, scene, cams = make(cfg_name, table_init=table_init, **over)
+    scene.scale_e += np.float32(scale_shift)
+    ds = device_scene(scene)
+    st = P.render(ds, cams, mode)
+    torch.cuda.synchronize()
+    r = oracle_view(scene, cams[0], mode)
+    H, W = cams[0].height, cams[0].width
+    res = compare_image(st.image[0].cpu().numpy(), r, mode, H, W)
+    _say("image", res, "entries", st.n_entries)
+    assert res["ok"], res
+    T_ref = r["T"].numpy().reshape(H, W)
+    assert float(np.abs(st.T[0].cpu().numpy() - T_ref).max()) < 1e-4
+
+
+def test_render_empty_scene_is_background():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.pos[1, :] = -10.0        # every Gaussian behind the camera
+    ds = device_scene(scene)
+    for mode in (O.TRAIN, O.RENDER):
+        st = P.render(ds, cams, mode)
+        torch.cuda.synchronize()
+        assert int(st.query["vis_count"].item()) == 0 and st.n_entries == 0
+        r = oracle_view(scene, cams[0], mode)
+        res = compare_image(st.image[0].cpu().numpy(), r, mode, 64, 64)
+        assert res["ok"], res
+
+
+def test_forward_is_deterministic():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    ds = device_scene(scene)
+    a = P.render(ds, cams, P.TRAIN)
+    b = P.render(ds, cams, P.TRAIN)
+    torch.cuda.synchronize()
+    assert torch.equal(a.image, b.image) and torch.equal(a.T, b.T) and torch.equal(a.last, b.last)
