@@ -275,15 +275,34 @@ def splat_extent(cov2d: torch.Tensor, opacity: torch.Tensor):
 
 # ---------------------------------------------------------------- compositing
 def _pairs_for_pixels(px, py, u, v, rx, ry):
-    """All (pixel, splat) pairs whose conservative box holds the pixel centre."""
+    """All (pixel, splat) pairs whose conservative box holds the pixel centre.
+    Pixels are grouped by 16x16 block; a block's candidates are the splats
+    whose box meets the block, then every pixel of the block is tested."""
     pi_list, si_list = [], []
-    for s in range(0, px.numel(), 256):
-        cx = px[s:s + 256, None] + 0.5
-        cy = py[s:s + 256, None] + 0.5
-        m = (torch.abs(cx - u[None]) <= rx[None]) & (torch.abs(cy - v[None]) <= ry[None])
-        pi, si = torch.nonzero(m, as_tuple=True)
-        pi_list.append(pi + s)
-        si_list.append(si)
+    bx = torch.div(px, 16, rounding_mode="floor")
+    by = torch.div(py, 16, rounding_mode="floor")
+    bid = by * (int(bx.max().item()) + 2 if px.numel() else 1) + bx
+    order = torch.argsort(bid, stable=True)
+    ub, counts = torch.unique_consecutive(bid[order], return_counts=True)
+    starts = torch.cumsum(counts, 0) - counts
+    for k in range(ub.numel()):
+        sel = order[starts[k]:starts[k] + counts[k]]
+        x0 = float(px[sel].min()) + 0.5
+        x1 = float(px[sel].max()) + 0.5
+        y0 = float(py[sel].min()) + 0.5
+        y1 = float(py[sel].max()) + 0.5
+        cand = torch.nonzero((u + rx >= x0) & (u - rx <= x1) & (v + ry >= y0) & (v - ry <= y1),
+                             as_tuple=True)[0]
+        if cand.numel() == 0:
+            continue
+        cx = px[sel, None].to(F64) + 0.5
+        cy = py[sel, None].to(F64) + 0.5
+        m = (torch.abs(cx - u[None, cand]) <= rx[None, cand]) & (torch.abs(cy - v[None, cand]) <= ry[None, cand])
+        a, b = torch.nonzero(m, as_tuple=True)
+        pi_list.append(sel[a])
+        si_list.append(cand[b])
+    if not pi_list:
+        return torch.zeros(0, dtype=torch.int64), torch.zeros(0, dtype=torch.int64)
     return torch.cat(pi_list), torch.cat(si_list)
 
 

@@ -148,7 +148,7 @@ def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool
     ws = ws or Workspace()
     n, V, L = scene.n, len(cams), scene.levels
     dev = scene.pos.device
-    q = dict(vis_count=torch.zeros(1, dtype=torch.int32, device=dev),
+    q = dict(vis_count=torch.empty(1, dtype=torch.int32, device=dev),
              vis_idx=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
              opacity=torch.empty(max(n, 1), device=dev), scale=torch.empty(3, max(n, 1), device=dev),
              quat=torch.empty(4, max(n, 1), device=dev), rgb=torch.empty(V, 3, max(n, 1), device=dev))
@@ -175,7 +175,7 @@ def project(scene: DeviceScene, cams, q, qout):
     sp = dict(rec=torch.empty(V, max(n, 1), 12, device=dev),
               rect=torch.empty(V, max(n, 1), 4, dtype=torch.int32, device=dev),
               depth=torch.empty(V, max(n, 1), device=dev),
-              total=torch.zeros(1, dtype=torch.int64, device=dev))
+              total=torch.empty(1, dtype=torch.int64, device=dev))
     cs = A.hyrf_splats(max(n, 1), q["vis_count"].data_ptr(), sp["rec"].data_ptr(), sp["rect"].data_ptr(),
                        sp["depth"].data_ptr(), sp["total"].data_ptr())
     g, cc = scene.c_gauss(), c_cameras(cams)
@@ -220,17 +220,32 @@ def composite(scene: Optional[DeviceScene], cams, splats_c, vals, ranges, mode: 
     return img, T, last, bg
 
 
+def _mark(events, name):
+    if events is not None:
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        events.setdefault(name, []).append(e)
+
+
 def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False, want_keys: bool = False,
-           ws: Optional[Workspace] = None) -> ForwardState:
+           ws: Optional[Workspace] = None, events: Optional[dict] = None) -> ForwardState:
     """The forward render step: query -> project -> bin/sort -> composite
-    (+ background).  One host read (the tile-entry count)."""
+    (+ background).  One host read (the tile-entry count).  `events`, if
+    given, collects torch.cuda.Event pairs (on the current stream, where
+    every kernel is launched) around each ABI call."""
     ws = ws or Workspace()
     V, W, H = len(cams), cams[0].width, cams[0].height
+    _mark(events, "query0")
     q, qout = query_fields(scene, cams, mode, debug_index, ws)
+    _mark(events, "query1")
     sp, spc = project(scene, cams, q, qout)
+    _mark(events, "project1")
     n_entries = int(sp["total"].item())
+    _mark(events, "bin0")
     keys, vals, ranges = bin_sort(cams, spc, max(scene.n, 1), n_entries, want_keys, ws)
+    _mark(events, "bin1")
     img, T, last, bg = composite(scene, cams, spc, vals, ranges, mode, ws)
+    _mark(events, "composite1")
     return ForwardState(mode=mode, V=V, W=W, H=H, n_entries=n_entries, query=q, splats=sp, vals=vals,
                         keys=keys, ranges=ranges, image=img, T=T, last=last, bg=bg,
                         c=dict(qout=qout, splats=spc))
