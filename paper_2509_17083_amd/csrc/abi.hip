@@ -15,6 +15,8 @@
 #include "project.h"
 #include "query.h"
 
+namespace { constexpr int POINTS_PER_ROUND_ABI = 128; }
+
 using namespace hyrf;
 
 namespace {
@@ -331,18 +333,136 @@ hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n, float
   return check_launch();
 }
 
+namespace {
+constexpr int BWD_MAX_BLOCKS = 512;
+
+struct BwdWs {
+  float *gs, *dgeo, *dcol, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;
+  size_t bytes;
+};
+
+BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max) {
+  size_t fg = 0, fc = 0, bg = 0, bc = 0, nw = 0;
+  bwd_weight_floats(f->levels, f->hidden, f->n_hidden, &fg, &fc, &bg, &bc, &nw);
+  Carve c(base);
+  BwdWs w;
+  const size_t nm = n_max > 0 ? (size_t)n_max : 1;
+  w.gs = c.take<float>((size_t)V * nm * 9);
+  w.dgeo = c.take<float>(nm * 8);
+  w.dcol = c.take<float>(nm * V * 3);
+  w.wf_geo = c.take<float>(fg);
+  w.wf_col = c.take<float>(fc);
+  w.wb_geo = c.take<float>(bg);
+  w.wb_col = c.take<float>(bc);
+  w.dw_part = c.take<float>((size_t)2 * BWD_MAX_BLOCKS * nw);
+  w.bytes = c.off;
+  return w;
+}
+}  // namespace
+
 size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max) {
-  (void)fields; (void)n_views; (void)n_max;
-  return 256;
+  if (!fields || !shape_supported(fields->levels, fields->hidden, fields->n_hidden) || n_views < 1) return 0;
+  return carve_bwd(nullptr, fields, n_views, n_max).bytes;
 }
 
 hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians* g,
                                  const hyrf_camera* cams, int32_t n_views, const hyrf_fwd_state* saved,
                                  const float* dL_drgb, const hyrf_grads* grads, void* ws,
                                  size_t ws_bytes, void* stream) {
-  (void)fields; (void)g; (void)cams; (void)n_views; (void)saved; (void)dL_drgb; (void)grads;
-  (void)ws; (void)ws_bytes; (void)stream;
-  return fail(HYRF_ERR_UNSUPPORTED, "backward not built yet");
+  hyrf_status s;
+  if ((s = check_fields(fields)) != HYRF_OK) return s;
+  if ((s = check_gauss(g)) != HYRF_OK) return s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  REQ(saved && saved->query && saved->splats, "saved forward state is incomplete");
+  const hyrf_query_out* q = saved->query;
+  const hyrf_splats* sp = saved->splats;
+  REQ(q->vis_count && q->vis_idx && q->opacity && q->scale && q->quat && q->rgb,
+      "saved query output is incomplete");
+  REQ(q->feat_geo && q->feat_rad, "backward needs the features saved by a TRAIN-mode query");
+  REQ(sp->rec && sp->rect && sp->n_max >= g->n && sp->n_max >= 1, "saved splats are incomplete");
+  REQ(((uintptr_t)sp->rec & 15) == 0 && ((uintptr_t)sp->rect & 15) == 0, "splats.rec / rect must be 16-byte aligned");
+  REQ(saved->vals && saved->tile_ranges && saved->T_final && saved->last && saved->bg_rgb,
+      "saved composite state (vals, tile_ranges, T_final, last, bg_rgb) is incomplete");
+  REQ(dL_drgb && grads, "dL_drgb / grads is NULL");
+  REQ((int64_t)n_views * sp->n_max < ((int64_t)1 << 31), "too many splats");
+  const size_t need = hyrf_backward_workspace_bytes(fields, n_views, sp->n_max);
+  REQ(ws && ws_bytes >= need, "backward workspace too small: %zu < %zu bytes", ws_bytes, need);
+  hipStream_t st = (hipStream_t)stream;
+  BwdWs w = carve_bwd(ws, fields, n_views, sp->n_max);
+  const int W = cams[0].width, H = cams[0].height;
+  BwdLaunch L{};
+  L.V = n_views;
+  L.comp.W = W;
+  L.comp.H = H;
+  L.comp.tiles_x = (W + TILE - 1) / TILE;
+  L.comp.tiles_y = (H + TILE - 1) / TILE;
+  L.comp.rec = sp->rec;
+  L.comp.n_rec = (uint32_t)((int64_t)n_views * sp->n_max);
+  L.comp.vals = saved->vals;
+  L.comp.ranges = saved->tile_ranges;
+  L.comp.T_final = saved->T_final;
+  L.comp.last = saved->last;
+  L.comp.bg = saved->bg_rgb;
+  L.comp.dL = dL_drgb;
+  L.comp.gs = w.gs;
+  L.n_gs = (int64_t)n_views * sp->n_max * 9;
+  const Cams cc = make_cams(cams, n_views);
+  L.proj.cams = cc;
+  L.proj.n = g->n;
+  L.proj.n_max = sp->n_max;
+  L.proj.count = q->vis_count;
+  L.proj.vis_idx = q->vis_idx;
+  L.proj.pos = g->pos;
+  L.proj.opacity = q->opacity;
+  L.proj.scale = q->scale;
+  L.proj.quat = q->quat;
+  L.proj.rgb = q->rgb;
+  L.proj.rect = sp->rect;
+  L.proj.gs = w.gs;
+  L.proj.g_pos = grads->pos;
+  L.proj.g_scale_e = grads->scale_e;
+  L.proj.g_opac_e = grads->opac_e;
+  L.proj.g_col_e = grads->col_e;
+  L.proj.dgeo = w.dgeo;
+  L.proj.dcol = w.dcol;
+  FieldBwdArgs& F = L.field;
+  F.grid = make_grid(fields);
+  F.cams = cc;
+  F.table_geo = (const float*)fields->table_geo;
+  F.table_rad = (const float*)fields->table_rad;
+  F.n = g->n;
+  F.count = q->vis_count;
+  F.vis_idx = q->vis_idx;
+  F.pos = g->pos;
+  F.rot_e = g->rot_e;
+  F.feat_geo = q->feat_geo;
+  F.feat_rad = q->feat_rad;
+  F.dgeo = w.dgeo;
+  F.dcol = w.dcol;
+  F.g_pos = grads->pos;
+  F.g_rot_e = grads->rot_e;
+  F.g_table_geo = grads->table_geo;
+  F.g_table_rad = grads->table_rad;
+  F.dw_part = w.dw_part;
+  F.W = W;
+  F.H = H;
+  F.T_final = saved->T_final;
+  F.dL = dL_drgb;
+  L.w_geo = fields->mlp_geo;
+  L.w_col = fields->mlp_col;
+  L.wf_geo = w.wf_geo;
+  L.wf_col = w.wf_col;
+  L.wb_geo = w.wb_geo;
+  L.wb_col = w.wb_col;
+  const int64_t rg = ((int64_t)g->n + POINTS_PER_ROUND_ABI - 1) / POINTS_PER_ROUND_ABI;
+  const int64_t rr = ((int64_t)n_views * W * H + POINTS_PER_ROUND_ABI - 1) / POINTS_PER_ROUND_ABI;
+  L.blocks_g = (int)(rg < 1 ? 1 : (rg > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rg));
+  L.blocks_r = (int)(rr < 1 ? 1 : (rr > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rr));
+  L.with_bg = true;
+  L.g_mlp_geo = grads->mlp_geo;
+  L.g_mlp_col = grads->mlp_col;
+  launch_backward(fields->levels, fields->hidden, fields->n_hidden, L, st);
+  return check_launch();
 }
 
 }  // extern "C"

@@ -8,4 +8,89 @@ size_t l1_ws_elems(int64_t n);
 void launch_l1(const float* img, const float* target, int64_t n, float* loss, float* grad, float* ws,
                hipStream_t st);
 
+// ---- backward.hip
+struct CompBwdArgs {
+  int W, H, tiles_x, tiles_y;
+  const float* rec;
+  uint32_t n_rec;
+  const uint32_t* vals;
+  const uint32_t* ranges;
+  const float* T_final;
+  const int32_t* last;
+  const float* bg;       // [V][3][H][W] background colours, or NULL
+  const float* dL;       // [V][3][H][W]
+  float* gs;             // [V*n_max][9]
+};
+
+struct ProjBwdArgs {
+  Cams cams;
+  int n, n_max;
+  const int32_t* count;
+  const int32_t* vis_idx;
+  const float* pos;
+  const float* opacity;
+  const float* scale;
+  const float* quat;
+  const float* rgb;
+  const int32_t* rect;
+  const float* gs;
+  float* g_pos;
+  float* g_scale_e;
+  float* g_opac_e;
+  float* g_col_e;
+  float* dgeo;           // [n][8] to the decoder adjoint
+  float* dcol;           // [n][V][3]
+};
+
+struct FieldBwdArgs {
+  GridP grid;
+  Cams cams;
+  const float* table_geo;
+  const float* table_rad;
+  const float* wf_geo;
+  const float* wf_col;
+  const float* wb_geo;
+  const float* wb_col;
+  int n;
+  const int32_t* count;
+  const int32_t* vis_idx;
+  const float* pos;
+  const float* rot_e;
+  const float* feat_geo;
+  const float* feat_rad;
+  const float* dgeo;
+  const float* dcol;
+  float* g_pos;
+  float* g_rot_e;
+  float* g_table_geo;
+  float* g_table_rad;
+  float* dw_part;
+  int n_w;
+  int W, H;
+  const float* T_final;
+  const float* dL;
+};
+
+struct BwdLaunch {
+  int V;
+  CompBwdArgs comp;
+  int64_t n_gs;
+  ProjBwdArgs proj;
+  FieldBwdArgs field;
+  const float* w_geo;
+  const float* w_col;
+  float* wf_geo;
+  float* wf_col;
+  float* wb_geo;
+  float* wb_col;
+  int blocks_g, blocks_r;
+  bool with_bg;
+  float* g_mlp_geo;
+  float* g_mlp_col;
+};
+
+void launch_backward(int L, int hid, int nh, const BwdLaunch& a, hipStream_t st);
+size_t bwd_weight_floats(int L, int hid, int nh, size_t* fwd_geo, size_t* fwd_col, size_t* bwd_geo,
+                         size_t* bwd_col, size_t* n_w);
+
 }  // namespace hyrf

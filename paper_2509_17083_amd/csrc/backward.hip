@@ -1,0 +1,630 @@
+// Adjoint of the render step (train mode).
+//
+//  k_composite_bwd  per 16x16 tile, back to front: the 3DGS blending adjoint
+//                   with the background term, transmittance recovered by
+//                   division from the final value; per-splat gradients of
+//                   (u, v, conic, opacity, rgb) summed over each wave's 64
+//                   pixels, then one atomic per value and wave.
+//  k_project_bwd    per surviving Gaussian, looping over views: EWA
+//                   projection adjoint (no atomics: one lane per Gaussian).
+//  k_field_bwd      per 16 Gaussians per wave (or 16 background pixels):
+//                   decoder adjoints on MFMA with dW accumulated through LDS
+//                   staging, hash-table scatter-add (atomics) and the
+//                   position gradient through the interpolation weights, the
+//                   contraction and the view direction.
+//  k_dw_reduce      sums the per-workgroup dW partials in a fixed order.
+#include "backward.h"
+#include "block.h"
+#include "composite.h"
+#include "field_bwd.h"
+#include "kernels.h"
+#include "query.h"
+
+namespace hyrf {
+
+constexpr int GS = 9;   // per-splat gradient record: u, v, conic a, b, c, opacity, r, g, b
+
+__global__ void k_zero_f32(float* p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = 0.f;
+}
+
+// ---------------------------------------------------------------- compositing
+__global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
+  __shared__ float4 s0[256], s1[256], s2[256];
+  __shared__ uint32_t sid[256];
+  __shared__ int smax[4];
+  const int tx = blockIdx.x, ty = blockIdx.y, v = blockIdx.z;
+  const int x = tx * TILE + (threadIdx.x & 15);
+  const int y = ty * TILE + (threadIdx.x >> 4);
+  const bool inside = x < a.W && y < a.H;
+  const int tile = (v * a.tiles_y + ty) * a.tiles_x + tx;
+  const uint32_t start = a.ranges[2 * tile];
+  const size_t HW = (size_t)a.W * a.H;
+  const size_t p = (size_t)y * a.W + x;
+  const float pxc = (float)x + 0.5f, pyc = (float)y + 0.5f;
+  float Tfin = 0.f, g0 = 0.f, g1 = 0.f, g2 = 0.f, bgd = 0.f;
+  int last = 0;
+  if (inside) {
+    Tfin = a.T_final[(size_t)v * HW + p];
+    last = a.last[(size_t)v * HW + p];
+    g0 = a.dL[((size_t)v * 3 + 0) * HW + p];
+    g1 = a.dL[((size_t)v * 3 + 1) * HW + p];
+    g2 = a.dL[((size_t)v * 3 + 2) * HW + p];
+    if (a.bg)
+      bgd = a.bg[((size_t)v * 3 + 0) * HW + p] * g0 + a.bg[((size_t)v * 3 + 1) * HW + p] * g1 +
+            a.bg[((size_t)v * 3 + 2) * HW + p] * g2;
+  }
+  // entries to walk: up to the furthest last contributor of the tile
+  int m = last;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) m = max(m, __shfl_xor(m, off, 64));
+  if (lane_id() == 0) smax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const int maxlast = max(max(smax[0], smax[1]), max(smax[2], smax[3]));
+  float T = Tfin;
+  float acc0 = 0.f, acc1 = 0.f, acc2 = 0.f, la = 0.f, lc0 = 0.f, lc1 = 0.f, lc2 = 0.f;
+  const float4* rec = reinterpret_cast<const float4*>(a.rec);
+  for (int b = ((maxlast - 1) / 256) * 256; maxlast > 0 && b >= 0; b -= 256) {
+    __syncthreads();
+    const int idx = b + (int)threadIdx.x;
+    if (idx < maxlast) {
+      const uint32_t id = a.vals[start + idx];
+      if (id < a.n_rec) {
+        s0[threadIdx.x] = rec[(size_t)id * 3];
+        s1[threadIdx.x] = rec[(size_t)id * 3 + 1];
+        s2[threadIdx.x] = rec[(size_t)id * 3 + 2];
+      } else {
+        s1[threadIdx.x] = make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      sid[threadIdx.x] = id;
+    }
+    __syncthreads();
+    const int nb = min(256, maxlast - b);
+    for (int k = nb - 1; k >= 0; --k) {
+      const float4 q0 = s0[k], q1 = s1[k];
+      const float dx = q0.x - pxc, dy = q0.y - pyc;
+      const float power = splat_power(q0.z, q0.w, q1.x, dx, dy);
+      const float G = __expf(power);
+      const float og = q1.y * G;
+      const float alpha = fminf(ALPHA_MAX, og);
+      const bool contrib = (b + k) < last && power <= 0.f && alpha >= ALPHA_MIN;
+      float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbb = 0.f;
+      if (contrib) {
+        const float cb = s2[k].x;
+        T = T / (1.f - alpha);
+        const float wgt = alpha * T;
+        gr = wgt * g0;
+        gg = wgt * g1;
+        gbb = wgt * g2;
+        acc0 = la * lc0 + (1.f - la) * acc0;
+        acc1 = la * lc1 + (1.f - la) * acc1;
+        acc2 = la * lc2 + (1.f - la) * acc2;
+        lc0 = q1.z; lc1 = q1.w; lc2 = cb;
+        float dLda = ((q1.z - acc0) * g0 + (q1.w - acc1) * g1 + (cb - acc2) * g2) * T;
+        la = alpha;
+        dLda += (-Tfin / (1.f - alpha)) * bgd;
+        if (og <= ALPHA_MAX) {
+          go = G * dLda;
+          const float dp = alpha * dLda;
+          gu = -dp * (q0.z * dx + q0.w * dy);
+          gv = -dp * (q1.x * dy + q0.w * dx);
+          ga = -0.5f * dp * dx * dx;
+          gb = -dp * dx * dy;
+          gc = -0.5f * dp * dy * dy;
+        }
+      }
+      if (__ballot(contrib)) {
+        gu = wave_sum_f32(gu); gv = wave_sum_f32(gv); ga = wave_sum_f32(ga);
+        gb = wave_sum_f32(gb); gc = wave_sum_f32(gc); go = wave_sum_f32(go);
+        gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gbb = wave_sum_f32(gbb);
+        if (lane_id() == 0) {
+          const uint32_t id = sid[k];
+          if (id < a.n_rec) {
+            float* o = a.gs + (size_t)id * GS;
+            atomicAdd(o + 0, gu); atomicAdd(o + 1, gv); atomicAdd(o + 2, ga);
+            atomicAdd(o + 3, gb); atomicAdd(o + 4, gc); atomicAdd(o + 5, go);
+            atomicAdd(o + 6, gr); atomicAdd(o + 7, gg); atomicAdd(o + 8, gbb);
+          }
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- projection
+__global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
+  const int s = blockIdx.x * 256 + threadIdx.x;
+  if (s >= *a.count) return;
+  const int n = a.n;
+  const int gi = a.vis_idx[s];
+  const float pxf = a.pos[gi], pyf = a.pos[n + gi], pzf = a.pos[2 * n + gi];
+  const float qw = a.quat[s], qx = a.quat[(size_t)n + s], qy = a.quat[2 * (size_t)n + s],
+              qz = a.quat[3 * (size_t)n + s];
+  const float Rq[3][3] = {{1.f - 2.f * (qy * qy + qz * qz), 2.f * (qx * qy - qw * qz), 2.f * (qx * qz + qw * qy)},
+                          {2.f * (qx * qy + qw * qz), 1.f - 2.f * (qx * qx + qz * qz), 2.f * (qy * qz - qw * qx)},
+                          {2.f * (qx * qz - qw * qy), 2.f * (qy * qz + qw * qx), 1.f - 2.f * (qx * qx + qy * qy)}};
+  float sc[3], s2[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    sc[d] = a.scale[(size_t)d * n + s];
+    s2[d] = sc[d] * sc[d];
+  }
+  float Sig[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int l = 0; l < 3; ++l) Sig[k][l] = Rq[k][0] * s2[0] * Rq[l][0] + Rq[k][1] * s2[1] * Rq[l][1] + Rq[k][2] * s2[2] * Rq[l][2];
+  float Gs[3][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+  float dpos[3] = {0.f, 0.f, 0.f};
+  float do_sum = 0.f;
+  float dce[3] = {0.f, 0.f, 0.f};
+  const float op = a.opacity[s];
+  for (int v = 0; v < a.cams.V; ++v) {
+    const int4 rc = reinterpret_cast<const int4*>(a.rect)[(size_t)v * a.n_max + s];
+    if (!(rc.z > rc.x && rc.w > rc.y)) {   // no tile entries in this view: no gradient
+#pragma unroll
+      for (int c = 0; c < 3; ++c) a.dcol[((size_t)s * a.cams.V + v) * 3 + c] = 0.f;
+      continue;
+    }
+    const float* gq = a.gs + ((size_t)v * a.n_max + s) * GS;
+    const float du = gq[0], dv = gq[1], dca = gq[2], dcb = gq[3], dcc = gq[4];
+    do_sum += gq[5];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float col = a.rgb[((size_t)v * 3 + c) * n + s];
+      const float dpre = gq[6 + c] * col * (1.f - col);
+      dce[c] += dpre;
+      a.dcol[((size_t)s * a.cams.V + v) * 3 + c] = dpre;
+    }
+    const CamP& c = a.cams.c[v];
+    double t[3];
+    cam_space_f64(c, (double)pxf, (double)pyf, (double)pzf, t);
+    const float tx = (float)t[0], ty = (float)t[1], tz = (float)t[2];
+    const float iz = 1.0f / tz;
+    const float j00 = c.fx * iz, j02 = -c.fx * tx * iz * iz;
+    const float j11 = c.fy * iz, j12 = -c.fy * ty * iz * iz;
+    float m0[3], m1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      m0[k] = j00 * c.R[k] + j02 * c.R[6 + k];
+      m1[k] = j11 * c.R[3 + k] + j12 * c.R[6 + k];
+    }
+    float Sm0[3], Sm1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      Sm0[k] = Sig[k][0] * m0[0] + Sig[k][1] * m0[1] + Sig[k][2] * m0[2];
+      Sm1[k] = Sig[k][0] * m1[0] + Sig[k][1] * m1[1] + Sig[k][2] * m1[2];
+    }
+    const float A = DILATION + (m0[0] * Sm0[0] + m0[1] * Sm0[1] + m0[2] * Sm0[2]);
+    const float B = m0[0] * Sm1[0] + m0[1] * Sm1[1] + m0[2] * Sm1[2];
+    const float C = DILATION + (m1[0] * Sm1[0] + m1[1] * Sm1[1] + m1[2] * Sm1[2]);
+    const float D = A * C - B * B;
+    const float iD = 1.f / D, iD2 = iD * iD;
+    // conic (C/D, -B/D, A/D) -> 2D covariance entries
+    const float dA = dca * (-C * C * iD2) + dcb * (B * C * iD2) + dcc * (iD - A * C * iD2);
+    const float dB = dca * (2.f * B * C * iD2) + dcb * (-iD - 2.f * B * B * iD2) + dcc * (2.f * A * B * iD2);
+    const float dC = dca * (iD - A * C * iD2) + dcb * (A * B * iD2) + dcc * (-A * A * iD2);
+    float dm0[3], dm1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      dm0[k] = 2.f * dA * Sm0[k] + dB * Sm1[k];
+      dm1[k] = 2.f * dC * Sm1[k] + dB * Sm0[k];
+    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l)
+        Gs[k][l] += dA * m0[k] * m0[l] + 0.5f * dB * (m0[k] * m1[l] + m1[k] * m0[l]) + dC * m1[k] * m1[l];
+    const float dJ00 = dm0[0] * c.R[0] + dm0[1] * c.R[1] + dm0[2] * c.R[2];
+    const float dJ02 = dm0[0] * c.R[6] + dm0[1] * c.R[7] + dm0[2] * c.R[8];
+    const float dJ11 = dm1[0] * c.R[3] + dm1[1] * c.R[4] + dm1[2] * c.R[5];
+    const float dJ12 = dm1[0] * c.R[6] + dm1[1] * c.R[7] + dm1[2] * c.R[8];
+    const float iz2 = iz * iz, iz3 = iz2 * iz;
+    const float dtx = du * c.fx * iz - dJ02 * c.fx * iz2;
+    const float dty = dv * c.fy * iz - dJ12 * c.fy * iz2;
+    const float dtz = -du * c.fx * tx * iz2 - dv * c.fy * ty * iz2 - dJ00 * c.fx * iz2 +
+                      dJ02 * 2.f * c.fx * tx * iz3 - dJ11 * c.fy * iz2 + dJ12 * 2.f * c.fy * ty * iz3;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) dpos[k] += c.R[k] * dtx + c.R[3 + k] * dty + c.R[6 + k] * dtz;
+  }
+  // Sigma = Rq diag(s^2) Rq^T
+  float dRq[3][3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int m = 0; m < 3; ++m)
+      dRq[k][m] = 2.f * (Gs[k][0] * Rq[0][m] + Gs[k][1] * Rq[1][m] + Gs[k][2] * Rq[2][m]) * s2[m];
+  float ds_pre[3];
+#pragma unroll
+  for (int m = 0; m < 3; ++m) {
+    float dd = 0.f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      dd += Rq[k][m] * (Gs[k][0] * Rq[0][m] + Gs[k][1] * Rq[1][m] + Gs[k][2] * Rq[2][m]);
+    const float dsc = 2.f * sc[m] * dd;
+    ds_pre[m] = dsc * sc[m] * (1.f - sc[m]);
+  }
+  const float dqw = 2.f * (-qz * dRq[0][1] + qy * dRq[0][2] + qz * dRq[1][0] - qx * dRq[1][2] - qy * dRq[2][0] + qx * dRq[2][1]);
+  const float dqx = 2.f * (qy * dRq[0][1] + qz * dRq[0][2] + qy * dRq[1][0] - 2.f * qx * dRq[1][1] - qw * dRq[1][2] +
+                           qz * dRq[2][0] + qw * dRq[2][1] - 2.f * qx * dRq[2][2]);
+  const float dqy = 2.f * (-2.f * qy * dRq[0][0] + qx * dRq[0][1] + qw * dRq[0][2] + qx * dRq[1][0] + qz * dRq[1][2] -
+                           qw * dRq[2][0] + qz * dRq[2][1] - 2.f * qy * dRq[2][2]);
+  const float dqz = 2.f * (-2.f * qz * dRq[0][0] - qw * dRq[0][1] + qx * dRq[0][2] + qw * dRq[1][0] - 2.f * qz * dRq[1][1] +
+                           qy * dRq[1][2] + qx * dRq[2][0] + qy * dRq[2][1]);
+  const float do_pre = do_sum * op * (1.f - op);
+  float* dg = a.dgeo + (size_t)s * 8;
+  dg[0] = do_pre;
+  dg[1] = ds_pre[0]; dg[2] = ds_pre[1]; dg[3] = ds_pre[2];
+  dg[4] = dqw; dg[5] = dqx; dg[6] = dqy; dg[7] = dqz;
+  if (a.g_pos)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * n + gi] += dpos[k];
+  if (a.g_opac_e) a.g_opac_e[gi] += do_pre;
+  if (a.g_scale_e)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_scale_e[(size_t)k * n + gi] += ds_pre[k];
+  if (a.g_col_e)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_col_e[(size_t)k * n + gi] += dce[k];
+}
+
+// ---------------------------------------------------------------- fields
+template <class Sh>
+__global__ void k_prep_weights(const float* wg, const float* wc, float* fg, float* fc, float* bg, float* bc) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  permute_mlp_fwd<Sh>(fg, wg, false, tid, stride);
+  permute_mlp_fwd<Sh>(fc, wc, true, tid, stride);
+  permute_mlp_bwd<Sh>(bg, wg, false, tid, stride);
+  permute_mlp_bwd<Sh>(bc, wc, true, tid, stride);
+}
+
+// Write the dW tiles of one layer (tile ids ID0 ..) owned by this wave.
+template <int ID0, int TO, int TI, int ACC>
+__device__ __forceinline__ void write_dw_layer(float* dst, int rows, int in, const v4f (&acc)[ACC], int w, int lane) {
+  const int j = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < TO * TI; ++t) {
+    const int id = ID0 + t;
+    if (id % BWD_WAVES != w) continue;
+    const int ot = t / TI, it = t % TI;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * ot + 4 * g + r, col = 16 * it + j;
+      if (row < rows && col < in) dst[row * in + col] = acc[id / BWD_WAVES][r];
+    }
+  }
+}
+
+template <class Sh, int ACC>
+__device__ void write_dw(float* part, const v4f (&acc)[ACC], int w, int lane) {
+  using B = BwdShape<Sh>;
+  constexpr int TH = Sh::HID / 16;
+  // geometry MLP
+  float* dst = part;
+  write_dw_layer<0, Sh::NT, B::TI_GEO1, ACC>(dst, Sh::HID, Sh::IN_GEO, acc, w, lane);
+  dst += Sh::HID * Sh::IN_GEO;
+  constexpr int G1 = Sh::NT * B::TI_GEO1;
+  if constexpr (Sh::NH == 2) {
+    write_dw_layer<G1, Sh::NT, TH, ACC>(dst, Sh::HID, Sh::HID, acc, w, lane);
+    dst += Sh::HID * Sh::HID;
+  }
+  constexpr int G2 = G1 + (Sh::NH - 1) * Sh::NT * TH;
+  write_dw_layer<G2, 1, TH, ACC>(dst, HYRF_GEO_OUT, Sh::HID, acc, w, lane);
+  dst += HYRF_GEO_OUT * Sh::HID;
+  // colour MLP
+  constexpr int C0 = B::TILES_GEO;
+  write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
+  dst += Sh::HID * Sh::IN_COL;
+  constexpr int C1 = C0 + Sh::NT * B::TI_COL1;
+  if constexpr (Sh::NH == 2) {
+    write_dw_layer<C1, Sh::NT, TH, ACC>(dst, Sh::HID, Sh::HID, acc, w, lane);
+    dst += Sh::HID * Sh::HID;
+  }
+  constexpr int C2 = C1 + (Sh::NH - 1) * Sh::NT * TH;
+  write_dw_layer<C2, 1, TH, ACC>(dst, HYRF_COL_OUT, Sh::HID, acc, w, lane);
+}
+
+// Contraction Jacobian transpose: dL/dp from dL/dx (App. A.1 map).
+__device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py, float pz, const float dx[3],
+                                             float dp[3]) {
+  const float q[3] = {(px - gp.center[0]) * gp.inv_half[0], (py - gp.center[1]) * gp.inv_half[1],
+                      (pz - gp.center[2]) * gp.inv_half[2]};
+  const float dm[3] = {0.25f * dx[0], 0.25f * dx[1], 0.25f * dx[2]};
+  const float n2 = q[0] * q[0] + q[1] * q[1] + q[2] * q[2];
+  float dq[3];
+  if (n2 > 1.f) {
+    const float nn = sqrtf(n2);
+    const float s = (2.f - 1.f / nn) / nn;
+    const float k = 2.f * (1.f - nn) / (n2 * n2);
+    const float qd = q[0] * dm[0] + q[1] * dm[1] + q[2] * dm[2];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dq[d] = s * dm[d] + k * q[d] * qd;
+  } else {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) dq[d] = dm[d];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) dp[d] = dq[d] * gp.inv_half[d];
+}
+
+template <class Sh, bool RAY>
+__global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
+  using B = BwdShape<Sh>;
+  constexpr int ACC = B::ACC;
+  __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
+  __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
+  const int lane = lane_id();
+  const int j = lane & 15, g = lane >> 4;
+  const int w = threadIdx.x / 64;
+  v4f accW[ACC];
+#pragma unroll
+  for (int k = 0; k < ACC; ++k) accW[k] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int HW = a.W * a.H;
+  const int count = RAY ? a.cams.V * HW : *a.count;
+  const int rounds = (count + POINTS_PER_ROUND - 1) / POINTS_PER_ROUND;
+  const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
+  const int V = a.cams.V;
+  for (int round = blockIdx.x; round < rounds; round += gridDim.x) {
+    const int item = round * POINTS_PER_ROUND + w * 16 + j;
+    const bool valid = item < count;
+    float fg[Sh::FPL], fr[Sh::FPL];
+    double x[3];
+    float pxf = 0.f, pyf = 0.f, pzf = 0.f;
+    int gi = 0, v_r = 0, pix = 0;
+    float dfr[Sh::FPL], dxg[Sh::S_GEO1];
+#pragma unroll
+    for (int s = 0; s < Sh::FPL; ++s) dfr[s] = 0.f;
+#pragma unroll
+    for (int s = 0; s < Sh::S_GEO1; ++s) dxg[s] = 0.f;
+    float dp_dir[3] = {0.f, 0.f, 0.f};
+    if constexpr (!RAY) {
+      gi = valid ? a.vis_idx[item] : a.vis_idx[0];
+      pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
+#pragma unroll
+      for (int k = 0; k < Sh::L / 4; ++k) {
+        const int lev = g + 4 * k;
+        float2 vg = make_float2(0.f, 0.f), vr = vg;
+        if (valid) {
+          vg = *reinterpret_cast<const float2*>(a.feat_geo + (size_t)item * 2 * Sh::L + 2 * lev);
+          vr = *reinterpret_cast<const float2*>(a.feat_rad + (size_t)item * 2 * Sh::L + 2 * lev);
+        }
+        fg[2 * k] = vg.x; fg[2 * k + 1] = vg.y;
+        fr[2 * k] = vr.x; fr[2 * k + 1] = vr.y;
+      }
+      // ---- geometry decoder adjoint
+      float x1g[Sh::S_GEO1];
+#pragma unroll
+      for (int s = 0; s < Sh::S_GEO1; ++s) x1g[s] = s < Sh::FPL ? fg[s] : 0.f;
+      float hg[Sh::NH][Sh::S_HID];
+      v4f og;
+      mlp_forward_keep<Sh, Sh::S_GEO1>(a.wf_geo, x1g, hg, og, lane);
+      v4f dg = v4f{0.f, 0.f, 0.f, 0.f};
+      if (valid && g == 0) {
+        const float* d = a.dgeo + (size_t)item * 8;
+        dg = v4f{d[0], d[1], d[2], d[3]};
+      }
+      if (valid && g == 1) {
+        // rotation rows: q = r / |r| with r = r_n (+ r_e)
+        const float* d = a.dgeo + (size_t)item * 8 + 4;
+        float r[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[k] = og[k] + (a.rot_e ? a.rot_e[(size_t)k * a.n + gi] : 0.f);
+        const float nr = sqrtf((r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]));
+        const float inr = 1.f / nr;
+        float q[4], qd = 0.f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          q[k] = r[k] * inr;
+          qd += q[k] * d[k];
+        }
+        float dr[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dr[k] = (d[k] - q[k] * qd) * inr;
+        dg = v4f{dr[0], dr[1], dr[2], dr[3]};
+        if (a.g_rot_e && a.rot_e)
+#pragma unroll
+          for (int k = 0; k < 4; ++k) a.g_rot_e[(size_t)k * a.n + gi] += dr[k];
+      }
+      mlp_backward<Sh, false, Sh::S_GEO1, ACC>(a.wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
+    } else {
+      pix = valid ? item : 0;
+      v_r = pix / HW;
+      const int rem = pix - v_r * HW;
+      const int yy = rem / a.W, xx = rem - yy * a.W;
+      double ps[3], d[3];
+      sphere_point_f64(a.cams.c[v_r], xx, yy, (double)a.grid.bg_radius, ps, d);
+      contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+      gather_lane<Sh::L, false>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
+      const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
+      pxf = (float)(d[0] / dn); pyf = (float)(d[1] / dn); pzf = (float)(d[2] / dn);
+      if (!valid) {
+#pragma unroll
+        for (int s = 0; s < Sh::FPL; ++s) fr[s] = 0.f;
+      }
+    }
+    // ---- colour decoder adjoint, once per view (one pass in ray mode)
+    const int nviews = RAY ? 1 : V;
+    for (int v = 0; v < nviews; ++v) {
+      float dir[3];
+      float inv_len = 0.f;
+      if constexpr (!RAY) {
+        float oc[3];
+        cam_center_f32(a.cams.c[v], oc);
+        dir[0] = pxf - oc[0]; dir[1] = pyf - oc[1]; dir[2] = pzf - oc[2];
+        inv_len = 1.0f / sqrtf((dir[0] * dir[0] + dir[1] * dir[1]) + dir[2] * dir[2]);
+        dir[0] *= inv_len; dir[1] *= inv_len; dir[2] *= inv_len;
+      } else {
+        dir[0] = pxf; dir[1] = pyf; dir[2] = pzf;
+      }
+      float pe[6];
+      pe_lane(g, dir[0], dir[1], dir[2], pe);
+      float x1c[Sh::S_COL1];
+#pragma unroll
+      for (int s = 0; s < Sh::S_COL1; ++s)
+        x1c[s] = !valid ? 0.f : (s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f));
+      float hc[Sh::NH][Sh::S_HID];
+      v4f oc4;
+      mlp_forward_keep<Sh, Sh::S_COL1>(a.wf_col, x1c, hc, oc4, lane);
+      v4f dc = v4f{0.f, 0.f, 0.f, 0.f};
+      if (valid && g == 0) {
+        if constexpr (!RAY) {
+          const float* d = a.dcol + ((size_t)item * V + v) * 3;
+          dc = v4f{d[0], d[1], d[2], 0.f};
+        } else {
+          const int rem = pix - v_r * HW;
+          const float T = a.T_final[pix];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const float cs = sigmoidf_(oc4[c]);
+            dc[c] = T * a.dL[((size_t)v_r * 3 + c) * HW + rem] * cs * (1.f - cs);
+          }
+        }
+      }
+      float dxc[Sh::S_COL1];
+      mlp_backward<Sh, true, Sh::S_COL1, ACC>(a.wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+#pragma unroll
+      for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
+      if constexpr (!RAY) {
+        // PE of octave g: d sin(a d)/dd = a cos(a d), d cos(a d)/dd = -a sin(a d)
+        const float af = 3.14159265358979323846f * (float)(1 << g);
+        float dd[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dd[k] = af * (dxc[Sh::FPL + k] * pe[3 + k] - dxc[Sh::FPL + 3 + k] * pe[k]);
+        const float dot = dir[0] * dd[0] + dir[1] * dd[1] + dir[2] * dd[2];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) dp_dir[k] += (dd[k] - dir[k] * dot) * inv_len;
+      }
+    }
+    // ---- hash tables: scatter-add and (Gaussians) position gradient
+    if constexpr (!RAY) contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
+    float dxv[3] = {0.f, 0.f, 0.f};
+    if (valid) {
+#pragma unroll
+      for (int k = 0; k < Sh::L / 4; ++k) {
+        const int lev = g + 4 * k;
+        const int res = a.grid.res[lev];
+        int ci[3];
+        float wv[3];
+        grid_cell(x, res, ci, wv);
+        const uint32_t side = (uint32_t)res + 1u;
+        const bool dgn = (a.grid.dense_geo >> lev) & 1u;
+        const bool drn = (a.grid.dense_rad >> lev) & 1u;
+        const float fr0 = dfr[2 * k], fr1 = dfr[2 * k + 1];
+        const float fg0 = RAY ? 0.f : dxg[2 * k], fg1 = RAY ? 0.f : dxg[2 * k + 1];
+        const float fres = (float)res;
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+          const uint32_t cx = (uint32_t)ci[0] + bx, cy = (uint32_t)ci[1] + by, cz = (uint32_t)ci[2] + bz;
+          const float wx = bx ? wv[0] : 1.f - wv[0];
+          const float wy = by ? wv[1] : 1.f - wv[1];
+          const float wz = bz ? wv[2] : 1.f - wv[2];
+          const float wc = (wx * wy) * wz;
+          const uint32_t rr = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
+          if (a.g_table_rad) {
+            float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
+            if (fr0 != 0.f) atomicAdd(tr, wc * fr0);
+            if (fr1 != 0.f) atomicAdd(tr + 1, wc * fr1);
+          }
+          if constexpr (!RAY) {
+            const uint32_t rg = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
+            if (a.g_table_geo) {
+              float* tgp = a.g_table_geo + ((size_t)lev * Tg + rg) * 2;
+              if (fg0 != 0.f) atomicAdd(tgp, wc * fg0);
+              if (fg1 != 0.f) atomicAdd(tgp + 1, wc * fg1);
+            }
+            const float2 vr = *reinterpret_cast<const float2*>(a.table_rad + ((size_t)lev * Tr + rr) * 2);
+            const float2 vg = *reinterpret_cast<const float2*>(a.table_geo + ((size_t)lev * Tg + rg) * 2);
+            const float val = (fg0 * vg.x + fg1 * vg.y) + (fr0 * vr.x + fr1 * vr.y);
+            dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);
+            dxv[1] += val * fres * (by ? 1.f : -1.f) * (wx * wz);
+            dxv[2] += val * fres * (bz ? 1.f : -1.f) * (wx * wy);
+          }
+        }
+      }
+    }
+    if constexpr (!RAY) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        dxv[k] += __shfl_xor(dxv[k], 16, 64);
+        dxv[k] += __shfl_xor(dxv[k], 32, 64);
+        dp_dir[k] += __shfl_xor(dp_dir[k], 16, 64);
+        dp_dir[k] += __shfl_xor(dp_dir[k], 32, 64);
+      }
+      if (valid && g == 0 && a.g_pos) {
+        float dp[3];
+        contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp[k] + dp_dir[k];
+      }
+    }
+  }
+  write_dw<Sh, ACC>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
+}
+
+__global__ void k_dw_reduce(const float* __restrict__ part, int nparts, int nw, float* __restrict__ gg,
+                            float* __restrict__ gc, int n_geo) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= nw) return;
+  float s = 0.f;
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * nw + i];
+  if (i < n_geo) {
+    if (gg) gg[i] += s;
+  } else if (gc) {
+    gc[i - n_geo] += s;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+template <class Sh>
+static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
+  using B = BwdShape<Sh>;
+  FieldBwdArgs a = L.field;
+  k_prep_weights<Sh><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
+  a.wf_geo = L.wf_geo; a.wf_col = L.wf_col; a.wb_geo = L.wb_geo; a.wb_col = L.wb_col;
+  a.n_w = Sh::N_GEO + Sh::N_COL;
+  // Gaussians
+  k_field_bwd<Sh, false><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+  int parts = L.blocks_g;
+  if (L.with_bg) {
+    FieldBwdArgs b = a;
+    b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
+    k_field_bwd<Sh, true><<<L.blocks_r, BWD_NT, 0, st>>>(b);
+    parts += L.blocks_r;
+  }
+  k_dw_reduce<<<nblk(a.n_w), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col, Sh::N_GEO);
+}
+
+void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st) {
+  // 1. per-splat gradient records
+  k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
+  dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
+  k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
+  // 2. projection adjoint
+  k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
+  // 3. decoders + tables (+ background)
+#define X(l, h, k) if (Lv == l && hid == h && nh == k) return launch_bwd_t<Shape<l, h, k>>(L, st);
+  X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
+#undef X
+}
+
+size_t bwd_weight_floats(int Lv, int hid, int nh, size_t* fwd_geo, size_t* fwd_col, size_t* bwd_geo,
+                         size_t* bwd_col, size_t* n_w) {
+#define X(l, h, k)                                                          \
+  if (Lv == l && hid == h && nh == k) {                                     \
+    using Sh = Shape<l, h, k>;                                              \
+    *fwd_geo = Sh::W_GEO; *fwd_col = Sh::W_COL;                             \
+    *bwd_geo = BwdShape<Sh>::WB_GEO; *bwd_col = BwdShape<Sh>::WB_COL;       \
+    *n_w = Sh::N_GEO + Sh::N_COL;                                           \
+    return *fwd_geo + *fwd_col + *bwd_geo + *bwd_col;                       \
+  }
+  X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
+#undef X
+  return 0;
+}
+
+}  // namespace hyrf

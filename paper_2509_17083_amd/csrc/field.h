@@ -50,15 +50,16 @@ __device__ __forceinline__ int first_layer_col(int s, int g, bool colour) {
   return -1;
 }
 
-// Fill LDS with one MLP's weights in the permuted A-operand order.
-// Layout per layer: [out_tile][s/4][lane][s%4].
+// Forward A-operand permutation of one MLP's weights.  Layout per layer:
+// [out_tile][s/4][lane][s%4]; element e of the whole MLP is written by the
+// caller's thread that owns it (tid, stride), so the same routine fills LDS
+// (per workgroup) or a global buffer (whole grid).
 template <class Sh>
-__device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colour) {
+__device__ void permute_mlp_fwd(float* dst, const float* __restrict__ W, bool colour, int tid, int stride) {
   const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
   const int in1 = colour ? Sh::IN_COL : Sh::IN_GEO;
   const int S1 = colour ? Sh::S_COL1 : Sh::S_GEO1;
-  // layer table: (lds offset, global offset, S, out tiles, rows, in, kind)
-  int lds_off = 0, g_off = 0;
+  int dst_off = 0, g_off = 0;
   for (int layer = 0; layer <= Sh::NH; ++layer) {
     const bool first = layer == 0;
     const bool last = layer == Sh::NH;
@@ -67,7 +68,7 @@ __device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colou
     const int rows = last ? n_out : Sh::HID;
     const int in = first ? in1 : Sh::HID;
     const int cnt = NTo * S * 64;
-    for (int e = threadIdx.x; e < cnt; e += blockDim.x) {
+    for (int e = tid; e < cnt; e += stride) {
       const int s4 = e & 3;
       const int lane = (e >> 2) & 63;
       const int rest = e >> 8;                 // ot * (S/4) + sq
@@ -76,14 +77,19 @@ __device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colou
       const int s = sq * 4 + s4;
       const int g = lane >> 4;
       const int row = ot * 16 + (lane & 15);
-      int col = first ? first_layer_col<Sh::L>(s, g, colour) : (16 * sq + 4 * g + s4);
+      const int col = first ? first_layer_col<Sh::L>(s, g, colour) : (16 * sq + 4 * g + s4);
       float val = 0.f;
       if (row < rows && col >= 0 && col < in) val = W[g_off + row * in + col];
-      lds[lds_off + e] = val;
+      dst[dst_off + e] = val;
     }
-    lds_off += cnt;
+    dst_off += cnt;
     g_off += rows * in;
   }
+}
+
+template <class Sh>
+__device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colour) {
+  permute_mlp_fwd<Sh>(lds, W, colour, threadIdx.x, blockDim.x);
 }
 
 // One layer: acc[ot] = sum_s W(ot, s) * x[s]   (x: this lane's B operands).

@@ -1,0 +1,222 @@
+// Adjoint of the tiny MLPs on MFMA, in the transposed lane layout of
+// field.h (a point's activations stay in the lanes that own the point).
+//
+//  * dX = W^T dY runs as D[in x points] = W^T[in x out] * dY[out x points];
+//    its A operand (W^T) is pre-permuted like the forward weights, with the
+//    rows of the first layer ordered so that the result lands in each lane's
+//    own input order (row 16*ot + 4g + r <-> the lane's input s = 4*ot + r).
+//  * dW = sum over points of dY (x) X needs the point index on the MFMA's k
+//    axis, i.e. across lane groups: the workgroup stages X and dY of its
+//    POINTS_PER_ROUND points in LDS ([point][feature], column-swizzled) and
+//    every wave accumulates a fixed subset of the 16x16 dW tiles over all
+//    staged points in registers, across every round of the persistent loop.
+#pragma once
+#include "field.h"
+
+namespace hyrf {
+
+constexpr int BWD_WAVES = 8;
+constexpr int BWD_NT = BWD_WAVES * 64;
+constexpr int POINTS_PER_ROUND = BWD_WAVES * 16;
+constexpr int STAGE_W = 64;                    // staged feature columns
+
+template <class Sh>
+struct BwdShape {
+  // dW tiles per layer: (rows/16 rounded up) x (in/16 rounded up)
+  static constexpr int TI_GEO1 = (Sh::IN_GEO + 15) / 16;
+  static constexpr int TI_COL1 = (Sh::IN_COL + 15) / 16;
+  static constexpr int TI_H = Sh::HID / 16;
+  static constexpr int TILES_GEO = Sh::NT * TI_GEO1 + (Sh::NH - 1) * Sh::NT * TI_H + TI_H;
+  static constexpr int TILES_COL = Sh::NT * TI_COL1 + (Sh::NH - 1) * Sh::NT * TI_H + TI_H;
+  static constexpr int TILES = TILES_GEO + TILES_COL;
+  static constexpr int ACC = (TILES + BWD_WAVES - 1) / BWD_WAVES;   // tiles per wave
+  // backward-permuted weight floats per MLP
+  static constexpr int WB_GEO = Sh::NT * 4 * 64 + (Sh::NH - 1) * Sh::NT * Sh::S_HID * 64 +
+                                (Sh::S_GEO1 / 4) * Sh::S_HID * 64;
+  static constexpr int WB_COL = Sh::NT * 4 * 64 + (Sh::NH - 1) * Sh::NT * Sh::S_HID * 64 +
+                                (Sh::S_COL1 / 4) * Sh::S_HID * 64;
+};
+
+// Backward A-operand permutation (W^T) of one MLP, layers in the order the
+// adjoint uses them: output layer, hidden layers from last to first, first
+// layer.  Layout per layer [row_tile][s/4][lane][s%4].
+template <class Sh>
+__device__ void permute_mlp_bwd(float* dst, const float* __restrict__ W, bool colour, int tid, int stride) {
+  const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
+  const int in1 = colour ? Sh::IN_COL : Sh::IN_GEO;
+  const int S1 = colour ? Sh::S_COL1 : Sh::S_GEO1;
+  // global offsets of the layers in the flat [out][in] weight list
+  int goff[4];
+  goff[0] = 0;
+  goff[1] = Sh::HID * in1;
+  goff[2] = goff[1] + (Sh::NH >= 2 ? Sh::HID * Sh::HID : 0);
+  const int g_out = Sh::NH == 2 ? goff[2] : goff[1];
+  int dst_off = 0;
+  // step = index into the adjoint sequence: 0 = output layer, 1..NH-1 =
+  // hidden layer NH-1..1 (weights W_k, k = NH - step), NH = first layer
+  for (int step = 0; step <= Sh::NH; ++step) {
+    const bool out_l = step == 0;
+    const bool first = step == Sh::NH;
+    const int S = out_l ? 4 : Sh::S_HID;                 // k steps: over the layer's output rows
+    const int RT = first ? S1 / 4 : Sh::NT;              // row tiles: over the layer's inputs
+    const int cnt = RT * S * 64;
+    for (int e = tid; e < cnt; e += stride) {
+      const int s4 = e & 3;
+      const int lane = (e >> 2) & 63;
+      const int rest = e >> 8;
+      const int sq = rest % (S / 4);
+      const int rt = rest / (S / 4);
+      const int kk = lane >> 4, i = lane & 15;
+      // k index = row of W (the layer's output unit)
+      const int wrow = out_l ? (4 * kk + s4) : (16 * sq + 4 * kk + s4);
+      float val = 0.f;
+      if (out_l) {
+        const int wcol = 16 * rt + i;                    // hidden unit
+        if (wrow < n_out) val = W[g_out + wrow * Sh::HID + wcol];
+      } else if (!first) {
+        const int wcol = 16 * rt + i;
+        val = W[goff[1] + wrow * Sh::HID + wcol];        // only NH == 2 reaches here
+      } else {
+        const int s_in = 4 * rt + (i & 3), g_in = i >> 2;
+        const int wcol = first_layer_col<Sh::L>(s_in, g_in, colour);
+        if (wcol >= 0 && wcol < in1) val = W[wrow * in1 + wcol];
+      }
+      dst[dst_off + e] = val;
+    }
+    dst_off += cnt;
+  }
+}
+
+// Forward pass that keeps the post-ReLU hidden activations (lane order).
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward_keep(const float* __restrict__ Wf, const float (&x1)[S1],
+                                                 float (&h)[Sh::NH][Sh::S_HID], v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer<Sh::NT, S1>(Wf, x1, acc, lane);
+  const float* W = Wf + Sh::NT * S1 * 64;
+  relu_to_inputs<Sh::NT>(acc, h[0]);
+#pragma unroll
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer<Sh::NT, Sh::S_HID>(W, h[k - 1], acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(acc, h[k]);
+  }
+  v4f o[1];
+  mfma_layer<1, Sh::S_HID>(W, h[Sh::NH - 1], o, lane);
+  out = o[0];
+}
+
+__device__ __forceinline__ int swz(int row, int col) { return row * STAGE_W + (col ^ ((row & 1) << 4)); }
+
+// Accumulate the dW tiles of one layer from the staged [point][feature]
+// arrays: tile (ot, it) += sum_p Y[p][16 ot + i] X[p][16 it + j].
+// Tile ids TB .. TB + TO*TI - 1; wave w owns ids with id % BWD_WAVES == w.
+template <int TB, int TO, int TI, int ACC>
+__device__ __forceinline__ void dw_tiles(const float* Xs, const float* Ys, v4f (&acc)[ACC], int w, int lane) {
+  const int kk = lane >> 4, i = lane & 15;
+#pragma unroll
+  for (int t = 0; t < TO * TI; ++t) {
+    const int id = TB + t;
+    if (id % BWD_WAVES != w) continue;
+    const int ot = t / TI, it = t % TI;
+    v4f c = acc[id / BWD_WAVES];
+#pragma unroll 8
+    for (int s = 0; s < POINTS_PER_ROUND / 4; ++s) {
+      const int p = 4 * s + kk;
+      const float av = Ys[swz(p, 16 * ot + i)];
+      const float bv = Xs[swz(p, 16 * it + i)];
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+    }
+    acc[id / BWD_WAVES] = c;
+  }
+}
+
+// Write rows (lane order: unit 16b + 4g + r = v[4b + r]) of this lane's point.
+template <int N>
+__device__ __forceinline__ void stage_units(float* S, int pt, int g, const float (&v)[N]) {
+#pragma unroll
+  for (int b = 0; b < N / 4; ++b)
+    *reinterpret_cast<float4*>(S + swz(pt, 16 * b + 4 * g)) = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+}
+
+// Write a first-layer input vector (lane order) at its canonical columns.
+template <class Sh, int S1>
+__device__ __forceinline__ void stage_inputs(float* S, int pt, int g, const float (&x)[S1], bool colour) {
+#pragma unroll
+  for (int s = 0; s < S1; ++s) {
+    const int col = first_layer_col<Sh::L>(s, g, colour);
+    if (col >= 0) S[swz(pt, col)] = x[s];
+  }
+}
+
+// Full adjoint of one MLP for the wave's 16 points.  dout: 16-row output
+// gradient tile (lane holds rows 4g..4g+3).  Returns dx (lane input order).
+// Contains workgroup barriers: every thread of the workgroup must call it
+// with the same template arguments.  TB0: first dW tile id of this MLP.
+template <class Sh, bool COL, int S1, int ACC>
+__device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const float (&x1)[S1],
+                                             const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                             float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
+                                             int w, int lane) {
+  using B = BwdShape<Sh>;
+  static_assert(S1 == (COL ? Sh::S_COL1 : Sh::S_GEO1), "first-layer width");
+  constexpr bool colour = COL;
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  const int j = lane & 15, g = lane >> 4;
+  const int pt = w * 16 + j;
+  // ---- output layer: dW_out += dout (x) h_last
+  {
+    float d4[4] = {dout[0], dout[1], dout[2], dout[3]};
+    *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) = make_float4(d4[0], d4[1], d4[2], d4[3]);
+    stage_units<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
+  }
+  __syncthreads();
+  constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
+  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+  __syncthreads();
+  float dh[Sh::S_HID];
+  {
+    float din[4] = {dout[0], dout[1], dout[2], dout[3]};
+    v4f acc[Sh::NT];
+    mfma_layer<Sh::NT, 4>(Wb, din, acc, lane);
+#pragma unroll
+    for (int b = 0; b < Sh::NT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[Sh::NH - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+  }
+  const float* W = Wb + Sh::NT * 4 * 64;
+  // ---- hidden layers, last to first (only NH == 2: one W_2)
+#pragma unroll
+  for (int k = Sh::NH - 1; k >= 1; --k) {
+    stage_units<Sh::S_HID>(Ys, pt, g, dh);
+    stage_units<Sh::S_HID>(Xs, pt, g, h[k - 1]);
+    __syncthreads();
+    constexpr int TB_H = TB0 + Sh::NT * TI1;
+    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+    __syncthreads();
+    v4f acc[Sh::NT];
+    mfma_layer<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+#pragma unroll
+    for (int b = 0; b < Sh::NT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+  }
+  // ---- first layer: dW_1 += dh (x) x, dx = W_1^T dh
+  stage_units<Sh::S_HID>(Ys, pt, g, dh);
+  stage_inputs<Sh, S1>(Xs, pt, g, x1, colour);
+  __syncthreads();
+  dw_tiles<TB0, Sh::NT, TI1, ACC>(Xs, Ys, accW, w, lane);
+  __syncthreads();
+  {
+    v4f acc[S1 / 4];
+    mfma_layer<S1 / 4, Sh::S_HID>(W, dh, acc, lane);
+#pragma unroll
+    for (int b = 0; b < S1 / 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dx[4 * b + r] = acc[b][r];
+  }
+}
+
+}  // namespace hyrf

@@ -261,3 +261,59 @@ def l1_loss(img: torch.Tensor, target: torch.Tensor, grad: bool = True, ws: Opti
     A.check("hyrf_l1_loss", lib.hyrf_l1_loss(_p(img), _p(target), n, _p(loss), _p(g), _p(w), w.numel(),
                                              _stream()))
     return loss, g
+
+
+def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.Tensor,
+                    grads: Optional[Dict[str, torch.Tensor]] = None, ws: Optional[Workspace] = None):
+    """Adjoint of a TRAIN-mode `render`: accumulates (+=) gradients of every
+    explicit parameter, both tables and both decoders into `grads` (zeroed
+    here when not given).  dL_drgb: (V, 3, H, W) float32."""
+    lib = A.load()
+    ws = ws or Workspace()
+    if st.mode != TRAIN:
+        raise ValueError("render_backward needs a TRAIN-mode forward state")
+    dL = dL_drgb.contiguous().float()
+    if grads is None:
+        z = torch.zeros_like
+        grads = dict(pos=z(scene.pos), scale_e=z(scene.scale_e),
+                     rot_e=None if scene.rot_e is None else z(scene.rot_e), opac_e=z(scene.opac_e),
+                     col_e=z(scene.col_e), table_geo=torch.zeros(scene.table_geo.shape, device="cuda"),
+                     table_rad=torch.zeros(scene.table_rad.shape, device="cuda"), mlp_geo=z(scene.mlp_geo),
+                     mlp_col=z(scene.mlp_col))
+    cg = A.hyrf_grads(*[_p(grads.get(k)) if grads.get(k) is not None else None for k in
+                        ("pos", "scale_e", "rot_e", "opac_e", "col_e", "table_geo", "table_rad", "mlp_geo",
+                         "mlp_col")])
+    qout, spc = st.c["qout"], st.c["splats"]
+    fs = A.hyrf_fwd_state(C.pointer(qout), C.pointer(spc), st.vals.data_ptr(), st.ranges.data_ptr(),
+                          st.T.data_ptr(), st.last.data_ptr(), st.bg.data_ptr())
+    f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
+    nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1))
+    w = ws.get("backward", nb)
+    A.check("hyrf_render_backward",
+            lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL), C.byref(cg),
+                                     _p(w), w.numel(), _stream()))
+    return grads
+
+
+class HyRFRender(torch.autograd.Function):
+    """Differentiable render step: forward = `render(..., TRAIN)`, backward =
+    `render_backward`.  Inputs are the scene's tensors; the scene object
+    carries the configuration.  Returns the (V, 3, H, W) image."""
+
+    @staticmethod
+    def forward(ctx, scene, cams, pos, scale_e, rot_e, opac_e, col_e, table_geo, table_rad, mlp_geo, mlp_col):
+        st = render(scene, cams, TRAIN)
+        ctx.scene, ctx.cams, ctx.st = scene, cams, st
+        ctx.has_rot = rot_e is not None
+        return st.image
+
+    @staticmethod
+    def backward(ctx, g_img):
+        gr = render_backward(ctx.scene, ctx.cams, ctx.st, g_img)
+        return (None, None, gr["pos"], gr["scale_e"], gr["rot_e"] if ctx.has_rot else None, gr["opac_e"],
+                gr["col_e"], gr["table_geo"], gr["table_rad"], gr["mlp_geo"], gr["mlp_col"])
+
+
+def render_differentiable(scene: DeviceScene, cams) -> torch.Tensor:
+    return HyRFRender.apply(scene, cams, scene.pos, scene.scale_e, scene.rot_e, scene.opac_e, scene.col_e,
+                            scene.table_geo, scene.table_rad, scene.mlp_geo, scene.mlp_col)

@@ -1,0 +1,124 @@
+"""GPU parity of the hand-written backward against the FP64 oracle's exact
+derivative (torch autograd of the oracle forward), through the C ABI.
+
+The loss is a seeded linear functional of the image, L = sum(w * C), with w
+zeroed on the oracle's knife-edge pixels (where a float32 predicate may
+legitimately flip), so both sides differentiate the same function.  Bar:
+per-tensor relative L2 error <= 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import hyrf_inputs as hi
+from oracle import hyrf_oracle as O
+from _hyrf_testutil import device_scene, knife_mask, make
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2509_17083_amd as P
+    return P
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _P()._abi.load()
+
+
+def _oracle_grads(scene, cam, w_img):
+    params, fields = O.from_scene(scene, requires_grad=True)
+    r = O.render_view(params, fields, cam, O.TRAIN, return_stats=True)
+    H, W = cam.height, cam.width
+    knife = knife_mask(r, O.TRAIN).reshape(H, W)
+    w = torch.from_numpy(w_img).double() * (~knife).double()[None]
+    img = r["rgb"].T.reshape(3, H, W)
+    L = torch.sum(img * w)
+    leaves = dict(pos=params.pos, scale_e=params.scale_e, rot_e=params.rot_e, opac_e=params.opac_e,
+                  col_e=params.col_e, table_geo=fields.table_geo, table_rad=fields.table_rad)
+    names = list(leaves) + ["mlp_geo", "mlp_col"]
+    tensors = list(leaves.values()) + [fields.mlp_geo, fields.mlp_col]
+    flat = []
+    for t in tensors:
+        flat.extend(t if isinstance(t, list) else [t])
+    gs = torch.autograd.grad(L, flat, allow_unused=True)
+    out, k = {}, 0
+    for nm, t in zip(names, tensors):
+        if isinstance(t, list):
+            out[nm] = torch.cat([(g if g is not None else torch.zeros_like(x)).reshape(-1)
+                                 for g, x in zip(gs[k:k + len(t)], t)])
+            k += len(t)
+        else:
+            out[nm] = gs[k] if gs[k] is not None else torch.zeros_like(t)
+            k += 1
+    return out, w.float().numpy(), float(knife.float().mean())
+
+
+def _compare(gpu, ref, tag):
+    errs = {}
+    for k, r in ref.items():
+        g = gpu[k]
+        if g is None:
+            continue
+        g = g.detach().cpu().double()
+        if k in ("pos", "scale_e", "rot_e", "col_e"):
+            g = g.T
+        r = r.reshape(g.shape)
+        nr = float(r.norm())
+        errs[k] = float((g - r).norm()) / max(nr, 1e-30) if nr > 0 else float(g.norm())
+    print(tag, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    return errs
+
+
+@pytest.mark.parametrize("cfg_name,over,table_init,scale_shift,with_rot", [
+    ("tiny", {}, 1.0, 1.0, True),
+    ("tiny", {}, None, 0.5, False),
+    ("c100k", {"n_gauss": 3000, "width": 96, "height": 72, "focal": 110.0, "log2_T_rad": 15}, 1.0, 1.0, True),
+])
+def test_backward_matches_oracle(cfg_name, over, table_init, scale_shift, with_rot):
+    print("case", cfg_name, over, table_init, scale_shift, with_rot, flush=True)
+    P = _P()
+    cfg, scene, cams = make(cfg_name, table_init=table_init, with_rot=with_rot, **over)
+    scene.scale_e += np.float32(scale_shift)
+    cam = cams[0]
+    w_img = hi.make_target_image((3, cam.height, cam.width), seed=17) - 0.5
+    ref, w_masked, kfrac = _oracle_grads(scene, cam, w_img)
+    ds = device_scene(scene)
+    st = P.render(ds, cams, P.TRAIN)
+    dL = torch.from_numpy(w_masked).cuda()[None]
+    gr = P.render_backward(ds, cams, st, dL)
+    torch.cuda.synchronize()
+    errs = _compare(gr, ref, f"{cfg_name} knife={kfrac:.3f}")
+    for k, e in errs.items():
+        assert e < 1e-3, (k, e)
+
+
+def test_backward_two_calls_accumulate():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    ds = device_scene(scene)
+    st = P.render(ds, cams, P.TRAIN)
+    dL = torch.from_numpy(hi.make_target_image((1, 3, 64, 64), seed=3) - 0.5).cuda()
+    g1 = P.render_backward(ds, cams, st, dL)
+    g1c = {k: v.clone() for k, v in g1.items() if v is not None}
+    P.render_backward(ds, cams, st, dL, grads=g1)
+    torch.cuda.synchronize()
+    for k, v in g1c.items():
+        assert torch.allclose(g1[k], 2 * v, rtol=1e-4, atol=1e-6 * float(v.abs().max()) + 1e-12), k
+
+
+def test_l1_loss_and_gradient():
+    P = _P()
+    rng = np.random.default_rng(4)
+    img = torch.from_numpy(rng.uniform(size=(2, 3, 50, 70)).astype(np.float32)).cuda()
+    tgt = torch.from_numpy(rng.uniform(size=(2, 3, 50, 70)).astype(np.float32)).cuda()
+    tgt[0, 0, 0, :5] = img[0, 0, 0, :5]          # ties: sign(0) = 0
+    loss, g = P.l1_loss(img, tgt)
+    torch.cuda.synchronize()
+    d = (img - tgt).double().cpu()
+    assert abs(float(loss) - float(d.abs().mean())) < 1e-6
+    want = torch.sign(d) / d.numel()
+    assert torch.equal(g.cpu().double(), want.float().double())
