@@ -32,23 +32,29 @@ def _ms(a, b):
 
 
 def cpu_baseline(scene, cam):
-    """The FP64 oracle (as it stands) on a bounded sample of the same frame:
-    field query + aggregation + projection of every 10th Gaussian, and
-    front-to-back blending (+ background) of 64 random 16x16 tiles against
-    that thinned set.  Scaled to a full frame: query/projection x10 (per
-    Gaussian), blending x10 (pair density) x tiles/64."""
+    """The FP64 oracle (as it stands) on a bounded sample of the same train
+    step: forward (field query + aggregation + projection of every 10th
+    Gaussian; blending + background of 64 random 16x16 tiles against that
+    thinned set), L1 loss on those pixels and the exact backward (autograd).
+    Scaled to a full frame: per-Gaussian work x10, blending x10 (pair
+    density) x tiles/64."""
     import numpy as np
     import torch
 
+    import hyrf_inputs as hi
     from oracle import hyrf_oracle as O
 
     torch.set_num_threads(os.cpu_count() or 1)
     stride = 10
     params, fields = O.from_scene(scene)
     sel = torch.arange(0, params.pos.shape[0], stride)
-    sub = O.Params(pos=params.pos[sel], scale_e=params.scale_e[sel],
-                   rot_e=None if params.rot_e is None else params.rot_e[sel],
-                   opac_e=params.opac_e[sel], col_e=params.col_e[sel])
+
+    def leaf(t):
+        return None if t is None else t[sel].clone().requires_grad_(True)
+    sub = O.Params(pos=leaf(params.pos), scale_e=leaf(params.scale_e), rot_e=leaf(params.rot_e),
+                   opac_e=leaf(params.opac_e), col_e=leaf(params.col_e))
+    for t in [fields.table_geo, fields.table_rad] + fields.mlp_geo + fields.mlp_col:
+        t.requires_grad_(True)
     rng = np.random.default_rng(0)
     tiles_x, tiles_y = (cam.width + 15) // 16, (cam.height + 15) // 16
     pick = rng.choice(tiles_x * tiles_y, size=64, replace=False)
@@ -61,31 +67,37 @@ def cpu_baseline(scene, cam):
                 if x < cam.width and y < cam.height:
                     pix.append((x, y))
     pix = torch.tensor(pix, dtype=torch.int64)
-    with torch.no_grad():
-        t0 = time.perf_counter()
-        keep = O.precull(sub.pos, cam)
-        idx = torch.nonzero(keep, as_tuple=True)[0]
-        q = O.query_gaussians(sub, fields, idx, cam)
-        pr = O.project(q["p"], q["scale"], q["quat"], cam)
-        t1 = time.perf_counter()
-        dk = O.depth_key(q["p"], cam)
-        order = torch.argsort(dk, stable=True)
-        rank = torch.empty_like(order)
-        rank[order] = torch.arange(order.numel())
-        rx, ry = O.splat_extent(pr["cov2d"], q["opacity"])
-        C, T = O.composite(pix[:, 0], pix[:, 1], pr["u"], pr["v"], pr["conic"], q["opacity"], q["rgb"],
-                           rank, rx, ry)
-        need = T > fields.tau_T
-        if bool(need.any()):
-            O.background_colour(pix[need, 0], pix[need, 1], cam, fields)
-        t2 = time.perf_counter()
-    full_ms = ((t1 - t0) * stride + (t2 - t1) * stride * (tiles_x * tiles_y) / len(pick)) * 1e3
-    return {"value": round(1000.0 / full_ms, 6), "unit": "frames/s (render forward)", "ms_per_frame": round(full_ms, 1),
-            "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle: query+projection of every {stride}th Gaussian ({len(sel)}), blending + "
-                      f"background of {len(pick)} random 16x16 tiles against that set; scaled x{stride} per "
-                      f"Gaussian and x{stride}x{tiles_x * tiles_y}/{len(pick)} for blending",
-            "sample_seconds": round(t2 - t0, 2)}
+    target = torch.from_numpy(hi.make_target_image((pix.shape[0], 3), seed=2001)).double()
+    t0 = time.perf_counter()
+    keep = O.precull(sub.pos, cam)
+    idx = torch.nonzero(keep, as_tuple=True)[0]
+    q = O.query_gaussians(sub, fields, idx, cam)
+    pr = O.project(q["p"], q["scale"], q["quat"], cam)
+    t1 = time.perf_counter()
+    dk = O.depth_key(q["p"], cam)
+    order = torch.argsort(dk, stable=True)
+    rank = torch.empty_like(order)
+    rank[order] = torch.arange(order.numel())
+    rx, ry = O.splat_extent(pr["cov2d"], q["opacity"])
+    C, T = O.composite(pix[:, 0], pix[:, 1], pr["u"], pr["v"], pr["conic"], q["opacity"], q["rgb"], rank, rx, ry)
+    cs = O.background_colour(pix[:, 0], pix[:, 1], cam, fields)
+    img = C + T[:, None] * cs
+    loss = O.l1_loss(img, target)
+    t2 = time.perf_counter()
+    loss.backward()
+    t3 = time.perf_counter()
+    # the backward's share is split like the forward's (gaussian part : pixel part)
+    fg, fp = t1 - t0, t2 - t1
+    bg_, bp = (t3 - t2) * fg / (fg + fp), (t3 - t2) * fp / (fg + fp)
+    scale_px = stride * (tiles_x * tiles_y) / len(pick)
+    full_ms = ((fg + bg_) * stride + (fp + bp) * scale_px) * 1e3
+    fwd_ms = (fg * stride + fp * scale_px) * 1e3
+    return {"value": round(1000.0 / full_ms, 7), "unit": "train steps/s (fwd+L1+bwd)", "ms_per_step": round(full_ms, 1),
+            "render_ms_per_frame": round(fwd_ms, 1), "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"FP64 oracle: every {stride}th Gaussian ({len(sel)}) through query+projection, "
+                      f"{len(pick)} random 16x16 tiles through blending + background + L1, autograd backward; "
+                      f"scaled x{stride} per Gaussian and x{stride}x{tiles_x * tiles_y}/{len(pick)} per pixel",
+            "sample_seconds": round(t3 - t0, 2)}
 
 
 def main():
@@ -116,43 +128,79 @@ def main():
     print(f"[bench] {cfg.name}: {cfg.n_gauss} Gaussians, {cfg.width}x{cfg.height}, views {cfg.n_views}",
           file=sys.stderr, flush=True)
 
-    for _ in range(args.warmup):
-        st = P.render(ds, cams, P.RENDER, ws=ws)
-    torch.cuda.synchronize()
-    events = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        st = P.render(ds, cams, P.RENDER, ws=ws, events=events)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
-    stage = {k: float(np.mean([_ms(a, b) for a, b in zip(events[k0], events[k1])]))
-             for k, k0, k1 in (("query", "query0", "query1"), ("project", "query1", "project1"),
-                               ("bin_sort", "bin0", "bin1"), ("composite", "bin1", "composite1"))}
-    print(f"[bench] render {ms:.3f} ms/frame; stages {stage}; entries {st.n_entries}", file=sys.stderr, flush=True)
+    H, W, V = cfg.height, cfg.width, cfg.n_views
+    target = torch.from_numpy(hi.make_target_image((V, 3, H, W), seed=2001)).cuda()
+    z = torch.zeros_like
+    grads = dict(pos=z(ds.pos), scale_e=z(ds.scale_e), rot_e=None if ds.rot_e is None else z(ds.rot_e),
+                 opac_e=z(ds.opac_e), col_e=z(ds.col_e), table_geo=z(ds.table_geo), table_rad=z(ds.table_rad),
+                 mlp_geo=z(ds.mlp_geo), mlp_col=z(ds.mlp_col))
 
-    # dominant kernel: the field query (gather-bound); algorithmic bytes per
-    # surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
+    def mark(ev, name):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record()
+        ev.setdefault(name, []).append(e)
+
+    def train_step(ev=None):
+        st = P.render(ds, cams, P.TRAIN, ws=ws, events=ev)
+        loss, dL = P.l1_loss(st.image, target, ws=ws)
+        for t in grads.values():
+            if t is not None:
+                t.zero_()
+        if ev is not None:
+            mark(ev, "bwd0")
+        P.render_backward(ds, cams, st, dL, grads=grads, ws=ws)
+        if ev is not None:
+            mark(ev, "bwd1")
+        return st, loss
+
+    def timed(fn, steps):
+        for _ in range(args.warmup):
+            fn(None)
+        torch.cuda.synchronize()
+        ev = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = fn(ev)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, ev, out
+
+    def stages(ev, keys):
+        return {k: float(np.mean([_ms(a, b) for a, b in zip(ev[k0], ev[k1])])) for k, k0, k1 in keys}
+
+    fwd_keys = (("query", "query0", "query1"), ("project", "query1", "project1"),
+                ("bin_sort", "bin0", "bin1"), ("composite", "bin1", "composite1"))
+    ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
+    st_train = stages(ev_t, fwd_keys + (("backward", "bwd0", "bwd1"),))
+    print(f"[bench] train step {ms_train:.3f} ms; stages {st_train}; loss {float(loss):.5f}; "
+          f"entries {st.n_entries}", file=sys.stderr, flush=True)
+    ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
+    st_render = stages(ev_r, fwd_keys)
+    print(f"[bench] render {ms_render:.3f} ms/frame; stages {st_render}", file=sys.stderr, flush=True)
+
+    # dominant forward kernel: the field query (gather-bound); algorithmic bytes
+    # per surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
     # + explicit parameters read (56 B) + aggregated properties written (44 B)
-    n_vis = int(st.query["vis_count"].item())
+    n_vis = int(st_r.query["vis_count"].item())
     per_g = 2 * cfg.levels * 8 * 2 * 4 + 56 + 44
-    q_ms = stage["query"]
+    q_ms = st_render["query"]
     achieved = n_vis * per_g / (q_ms * 1e-3) / 1e9
     roof = {"kernel": "k_field_query", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
             "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
 
-    out = {"metric": METRIC, "value": round(1000.0 / ms, 3), "unit": "frames/s (render forward step)",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+    out = {"metric": METRIC, "value": round(1000.0 / ms_train, 3), "unit": "train steps/s (fwd+L1+bwd)",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_train, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic (seeded), inputs resident in HBM",
            "config": {"workload": f"{cfg.name}: {cfg.n_gauss} Gaussians, {cfg.width}x{cfg.height}, "
                                   f"{cfg.n_views} view(s), L={cfg.levels}, T_rad=2^{cfg.log2_T_rad}, "
-                                  f"MLP {cfg.n_hidden}x{cfg.hidden}, FP32 fields, render mode",
-                      "step": "render forward (pre-cull, field query, projection, binning sort, composite, "
-                              "background)"},
-           "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+                                  f"MLP {cfg.n_hidden}x{cfg.hidden}, FP32 fields",
+                      "step": "train: pre-cull, field query, projection, binning sort, composite, background, "
+                              "L1 loss, full backward (gradient buffers zeroed inside the step)"},
+           "train_step_ms": round(ms_train, 4), "render_ms": round(ms_render, 4),
+           "render_fps": round(1000.0 / ms_render, 2),
+           "stage_ms_train": {k: round(v, 4) for k, v in st_train.items()},
+           "stage_ms_render": {k: round(v, 4) for k, v in st_render.items()},
            "tile_entries": st.n_entries,
            "roofline": roof}
     if not args.no_cpu_baseline:
