@@ -107,6 +107,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 256 MiB device copy (torch) 5 times: the reference kernel for "
+                         "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--render-only", action="store_true", help="time only the render-mode forward")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the render step of this "
@@ -115,6 +119,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.calibrate_copy:
+        torch.cuda.set_device(0)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": src.numel() * 4,
+                          "bytes_written": dst.numel() * 4, "launches": 5}))
+        return
 
     import hyrf_inputs as hi
     import paper_2509_17083_amd as P

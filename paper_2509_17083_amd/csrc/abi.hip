@@ -337,7 +337,7 @@ namespace {
 constexpr int BWD_MAX_BLOCKS = 512;
 
 struct BwdWs {
-  float *gs, *dgeo, *dcol, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;
+  float *gs, *dgeo, *dcol, *dfeat_geo, *dfeat_rad, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;
   size_t bytes;
 };
 
@@ -350,6 +350,8 @@ BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max) {
   w.gs = c.take<float>((size_t)V * nm * 9);
   w.dgeo = c.take<float>(nm * 8);
   w.dcol = c.take<float>(nm * V * 3);
+  w.dfeat_geo = c.take<float>(nm * 2 * f->levels);
+  w.dfeat_rad = c.take<float>(nm * 2 * f->levels);
   w.wf_geo = c.take<float>(fg);
   w.wf_col = c.take<float>(fc);
   w.wb_geo = c.take<float>(bg);
@@ -439,6 +441,8 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   F.feat_rad = q->feat_rad;
   F.dgeo = w.dgeo;
   F.dcol = w.dcol;
+  F.dfeat_geo = w.dfeat_geo;
+  F.dfeat_rad = w.dfeat_rad;
   F.g_pos = grads->pos;
   F.g_rot_e = grads->rot_e;
   F.g_table_geo = grads->table_geo;

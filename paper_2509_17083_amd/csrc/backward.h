@@ -60,6 +60,8 @@ struct FieldBwdArgs {
   const float* feat_rad;
   const float* dgeo;
   const float* dcol;
+  float* dfeat_geo;      // [n][2L] feature gradients handed to the grid adjoint
+  float* dfeat_rad;
   float* g_pos;
   float* g_rot_e;
   float* g_table_geo;
@@ -69,6 +71,21 @@ struct FieldBwdArgs {
   int W, H;
   const float* T_final;
   const float* dL;
+};
+
+struct GridBwdArgs {
+  GridP grid;
+  int n;
+  const int32_t* count;
+  const int32_t* vis_idx;
+  const float* pos;
+  const float* table_geo;
+  const float* table_rad;
+  const float* dfeat_geo;
+  const float* dfeat_rad;
+  float* g_pos;
+  float* g_table_geo;
+  float* g_table_rad;
 };
 
 struct BwdLaunch {

@@ -497,10 +497,27 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         for (int k = 0; k < 3; ++k) dp_dir[k] += (dd[k] - dir[k] * dot) * inv_len;
       }
     }
-    // ---- hash tables: scatter-add and (Gaussians) position gradient
-    if constexpr (!RAY) contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
-    float dxv[3] = {0.f, 0.f, 0.f};
-    if (valid) {
+    if constexpr (!RAY) {
+      // decoder-side results: feature gradients (canonical order) for the
+      // grid adjoint, and the view-direction part of the position gradient
+      if (valid) {
+#pragma unroll
+        for (int k = 0; k < Sh::L / 4; ++k) {
+          const int lev = g + 4 * k;
+          *reinterpret_cast<float2*>(a.dfeat_geo + (size_t)item * 2 * Sh::L + 2 * lev) = make_float2(dxg[2 * k], dxg[2 * k + 1]);
+          *reinterpret_cast<float2*>(a.dfeat_rad + (size_t)item * 2 * Sh::L + 2 * lev) = make_float2(dfr[2 * k], dfr[2 * k + 1]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        dp_dir[k] += __shfl_xor(dp_dir[k], 16, 64);
+        dp_dir[k] += __shfl_xor(dp_dir[k], 32, 64);
+      }
+      if (valid && g == 0 && a.g_pos)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k];
+    } else if (valid && a.g_table_rad) {
+      // background points: scatter-add into the radiance table only
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
@@ -509,59 +526,98 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         float wv[3];
         grid_cell(x, res, ci, wv);
         const uint32_t side = (uint32_t)res + 1u;
-        const bool dgn = (a.grid.dense_geo >> lev) & 1u;
         const bool drn = (a.grid.dense_rad >> lev) & 1u;
         const float fr0 = dfr[2 * k], fr1 = dfr[2 * k + 1];
-        const float fg0 = RAY ? 0.f : dxg[2 * k], fg1 = RAY ? 0.f : dxg[2 * k + 1];
-        const float fres = (float)res;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
           const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-          const uint32_t cx = (uint32_t)ci[0] + bx, cy = (uint32_t)ci[1] + by, cz = (uint32_t)ci[2] + bz;
-          const float wx = bx ? wv[0] : 1.f - wv[0];
-          const float wy = by ? wv[1] : 1.f - wv[1];
-          const float wz = bz ? wv[2] : 1.f - wv[2];
-          const float wc = (wx * wy) * wz;
-          const uint32_t rr = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-          if (a.g_table_rad) {
-            float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
-            if (fr0 != 0.f) atomicAdd(tr, wc * fr0);
-            if (fr1 != 0.f) atomicAdd(tr + 1, wc * fr1);
-          }
-          if constexpr (!RAY) {
-            const uint32_t rg = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
-            if (a.g_table_geo) {
-              float* tgp = a.g_table_geo + ((size_t)lev * Tg + rg) * 2;
-              if (fg0 != 0.f) atomicAdd(tgp, wc * fg0);
-              if (fg1 != 0.f) atomicAdd(tgp + 1, wc * fg1);
-            }
-            const float2 vr = *reinterpret_cast<const float2*>(a.table_rad + ((size_t)lev * Tr + rr) * 2);
-            const float2 vg = *reinterpret_cast<const float2*>(a.table_geo + ((size_t)lev * Tg + rg) * 2);
-            const float val = (fg0 * vg.x + fg1 * vg.y) + (fr0 * vr.x + fr1 * vr.y);
-            dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);
-            dxv[1] += val * fres * (by ? 1.f : -1.f) * (wx * wz);
-            dxv[2] += val * fres * (bz ? 1.f : -1.f) * (wx * wy);
-          }
+          const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
+          const uint32_t rr = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn,
+                                         side, a.grid.mask_rad);
+          float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
+          if (fr0 != 0.f) atomicAdd(tr, wc * fr0);
+          if (fr1 != 0.f) atomicAdd(tr + 1, wc * fr1);
         }
-      }
-    }
-    if constexpr (!RAY) {
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        dxv[k] += __shfl_xor(dxv[k], 16, 64);
-        dxv[k] += __shfl_xor(dxv[k], 32, 64);
-        dp_dir[k] += __shfl_xor(dp_dir[k], 16, 64);
-        dp_dir[k] += __shfl_xor(dp_dir[k], 32, 64);
-      }
-      if (valid && g == 0 && a.g_pos) {
-        float dp[3];
-        contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp[k] + dp_dir[k];
       }
     }
   }
   write_dw<Sh, ACC>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
+}
+
+// Hash-grid adjoint of the surviving Gaussians: 16 lanes per Gaussian, one
+// level per lane.  Scatter-add of w_c * dL/df into both tables (atomics) and
+// dL/dx = sum_c (dL/df . table[c]) dw_c/dx, reduced over the levels, then the
+// contraction Jacobian -> dL/dp.
+__global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
+  const int lev = threadIdx.x & 15;
+  const int item = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int count = *a.count;
+  const bool valid = item < count && lev < a.grid.L;
+  float dxv[3] = {0.f, 0.f, 0.f};
+  int gi = 0;
+  float pxf = 0.f, pyf = 0.f, pzf = 0.f;
+  if (item < count) {
+    gi = a.vis_idx[item];
+    pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
+  }
+  if (valid) {
+    const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
+    double x[3];
+    contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
+    const int res = a.grid.res[lev];
+    int ci[3];
+    float wv[3];
+    grid_cell(x, res, ci, wv);
+    const uint32_t side = (uint32_t)res + 1u;
+    const bool dgn = (a.grid.dense_geo >> lev) & 1u;
+    const bool drn = (a.grid.dense_rad >> lev) & 1u;
+    const float2 dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
+    const float2 dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
+    const float fres = (float)res;
+    uint32_t rg[8], rr[8];
+    float2 vg[8], vr[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const uint32_t cx = (uint32_t)ci[0] + (c & 1), cy = (uint32_t)ci[1] + ((c >> 1) & 1),
+                     cz = (uint32_t)ci[2] + ((c >> 2) & 1);
+      rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
+      rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
+      vg[c] = *reinterpret_cast<const float2*>(a.table_geo + ((size_t)lev * Tg + rg[c]) * 2);
+      vr[c] = *reinterpret_cast<const float2*>(a.table_rad + ((size_t)lev * Tr + rr[c]) * 2);
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+      const float wx = bx ? wv[0] : 1.f - wv[0];
+      const float wy = by ? wv[1] : 1.f - wv[1];
+      const float wz = bz ? wv[2] : 1.f - wv[2];
+      const float wc = (wx * wy) * wz;
+      if (a.g_table_geo) {
+        float* p = a.g_table_geo + ((size_t)lev * Tg + rg[c]) * 2;
+        if (dg.x != 0.f) atomicAdd(p, wc * dg.x);
+        if (dg.y != 0.f) atomicAdd(p + 1, wc * dg.y);
+      }
+      if (a.g_table_rad) {
+        float* p = a.g_table_rad + ((size_t)lev * Tr + rr[c]) * 2;
+        if (dr.x != 0.f) atomicAdd(p, wc * dr.x);
+        if (dr.y != 0.f) atomicAdd(p + 1, wc * dr.y);
+      }
+      const float val = (dg.x * vg[c].x + dg.y * vg[c].y) + (dr.x * vr[c].x + dr.y * vr[c].y);
+      dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);
+      dxv[1] += val * fres * (by ? 1.f : -1.f) * (wx * wz);
+      dxv[2] += val * fres * (bz ? 1.f : -1.f) * (wx * wy);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) dxv[k] += __shfl_xor(dxv[k], off, 64);
+  if (item < count && lev == 0 && a.g_pos) {
+    float dp[3];
+    contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp[k];
+  }
 }
 
 __global__ void k_dw_reduce(const float* __restrict__ part, int nparts, int nw, float* __restrict__ gg,
@@ -589,6 +645,22 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
   a.n_w = Sh::N_GEO + Sh::N_COL;
   // Gaussians
   k_field_bwd<Sh, false><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+  {
+    GridBwdArgs gb{};
+    gb.grid = a.grid;
+    gb.n = a.n;
+    gb.count = a.count;
+    gb.vis_idx = a.vis_idx;
+    gb.pos = a.pos;
+    gb.table_geo = a.table_geo;
+    gb.table_rad = a.table_rad;
+    gb.dfeat_geo = a.dfeat_geo;
+    gb.dfeat_rad = a.dfeat_rad;
+    gb.g_pos = a.g_pos;
+    gb.g_table_geo = a.g_table_geo;
+    gb.g_table_rad = a.g_table_rad;
+    k_grid_bwd<<<(unsigned)((a.n + 15) / 16 > 0 ? (a.n + 15) / 16 : 1), 256, 0, st>>>(gb);
+  }
   int parts = L.blocks_g;
   if (L.with_bg) {
     FieldBwdArgs b = a;
