@@ -38,6 +38,7 @@ def _oracle_grads(scene, cam, w_img):
     L = torch.sum(img * w)
     leaves = dict(pos=params.pos, scale_e=params.scale_e, rot_e=params.rot_e, opac_e=params.opac_e,
                   col_e=params.col_e, table_geo=fields.table_geo, table_rad=fields.table_rad)
+    leaves = {k: v for k, v in leaves.items() if v is not None}
     names = list(leaves) + ["mlp_geo", "mlp_col"]
     tensors = list(leaves.values()) + [fields.mlp_geo, fields.mlp_col]
     flat = []
