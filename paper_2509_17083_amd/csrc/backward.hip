@@ -516,8 +516,12 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       if (valid && g == 0 && a.g_pos)
 #pragma unroll
         for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k];
-    } else if (valid && a.g_table_rad) {
-      // background points: scatter-add into the radiance table only
+    } else if (a.g_table_rad) {
+      // Background points: scatter-add into the radiance table only.  The 16
+      // pixels of a lane group are consecutive in a row, so at the coarse
+      // levels they usually share a cell: when all 16 rows of a corner agree,
+      // the group sums in registers and issues one atomic instead of 16.
+      const uint64_t gmask = 0xFFFFull << (16 * g);
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
@@ -527,16 +531,33 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         grid_cell(x, res, ci, wv);
         const uint32_t side = (uint32_t)res + 1u;
         const bool drn = (a.grid.dense_rad >> lev) & 1u;
-        const float fr0 = dfr[2 * k], fr1 = dfr[2 * k + 1];
+        const float fr0 = valid ? dfr[2 * k] : 0.f, fr1 = valid ? dfr[2 * k + 1] : 0.f;
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
           const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
           const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
-          const uint32_t rr = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn,
-                                         side, a.grid.mask_rad);
-          float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
-          if (fr0 != 0.f) atomicAdd(tr, wc * fr0);
-          if (fr1 != 0.f) atomicAdd(tr + 1, wc * fr1);
+          const uint32_t rr0 = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn,
+                                          side, a.grid.mask_rad);
+          const uint32_t key0 = __shfl(rr0, lane & 48, 64);
+          const uint32_t rr = valid ? rr0 : key0;
+          float v0 = wc * fr0, v1 = wc * fr1;
+          const uint64_t same = __ballot(rr == key0) & gmask;
+          if (same == gmask) {
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {
+              v0 += __shfl_xor(v0, off, 64);
+              v1 += __shfl_xor(v1, off, 64);
+            }
+            if (j == 0) {
+              float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
+              if (v0 != 0.f) atomicAdd(tr, v0);
+              if (v1 != 0.f) atomicAdd(tr + 1, v1);
+            }
+          } else if (valid) {
+            float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
+            if (v0 != 0.f) atomicAdd(tr, v0);
+            if (v1 != 0.f) atomicAdd(tr + 1, v1);
+          }
         }
       }
     }
