@@ -349,15 +349,55 @@ __device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py
   for (int d = 0; d < 3; ++d) dp[d] = dq[d] * gp.inv_half[d];
 }
 
+constexpr int MAP_SLOTS = 2048;
+constexpr uint32_t MAP_EMPTY = 0xFFFFFFFFu;
+constexpr int MAP_MAX_RES = 410;   // levels up to this resolution use the workgroup map
+
+// Add (v0, v1) to table row `row` of level `lev`: through the workgroup map
+// when `use_map` (linear probing, at most 8 slots), else (or when the probe
+// finds no slot) with global atomics.
+__device__ __forceinline__ void map_or_global_add(uint32_t* mk, float2* mv, float* gtab, int lev, uint32_t T,
+                                                  uint32_t row, float v0, float v1, bool use_map) {
+  if (v0 == 0.f && v1 == 0.f) return;
+  const uint32_t key = (uint32_t)lev * T + row;
+  if (use_map) {
+    uint32_t h = (key * 2654435761u) >> (32 - 11);
+#pragma unroll 1
+    for (int probe = 0; probe < 8; ++probe) {
+      const uint32_t prev = atomicCAS(&mk[h], MAP_EMPTY, key);
+      if (prev == MAP_EMPTY || prev == key) {
+        atomicAdd(&mv[h].x, v0);
+        atomicAdd(&mv[h].y, v1);
+        return;
+      }
+      h = (h + 1) & (MAP_SLOTS - 1);
+    }
+  }
+  float* tr = gtab + (size_t)key * 2;
+  if (v0 != 0.f) atomicAdd(tr, v0);
+  if (v1 != 0.f) atomicAdd(tr + 1, v1);
+}
+
 template <class Sh, bool RAY>
 __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   using B = BwdShape<Sh>;
   constexpr int ACC = B::ACC;
   __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
   __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
+  // background mode: workgroup-private accumulation of the coarse levels'
+  // table gradients (open addressing on key = level * T + row)
+  __shared__ uint32_t map_key[RAY ? MAP_SLOTS : 1];
+  __shared__ float2 map_val[RAY ? MAP_SLOTS : 1];
   const int lane = lane_id();
   const int j = lane & 15, g = lane >> 4;
   const int w = threadIdx.x / 64;
+  if constexpr (RAY) {
+    for (int k = threadIdx.x; k < MAP_SLOTS; k += BWD_NT) {
+      map_key[k] = MAP_EMPTY;
+      map_val[k] = make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+  }
   v4f accW[ACC];
 #pragma unroll
   for (int k = 0; k < ACC; ++k) accW[k] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -366,7 +406,14 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   const int rounds = (count + POINTS_PER_ROUND - 1) / POINTS_PER_ROUND;
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const int V = a.cams.V;
-  for (int round = blockIdx.x; round < rounds; round += gridDim.x) {
+  // Gaussians: rounds strided over workgroups; background pixels: each
+  // workgroup owns a contiguous band of rounds (image rows), so the coarse
+  // cells it touches repeat and stay in its private map
+  const int per_blk = (rounds + (int)gridDim.x - 1) / (int)gridDim.x;
+  const int r_begin = RAY ? (int)blockIdx.x * per_blk : (int)blockIdx.x;
+  const int r_end = RAY ? min(rounds, r_begin + per_blk) : rounds;
+  const int r_step = RAY ? 1 : (int)gridDim.x;
+  for (int round = r_begin; round < r_end; round += r_step) {
     const int item = round * POINTS_PER_ROUND + w * 16 + j;
     const bool valid = item < count;
     float fg[Sh::FPL], fr[Sh::FPL];
@@ -548,16 +595,23 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
               v0 += __shfl_xor(v0, off, 64);
               v1 += __shfl_xor(v1, off, 64);
             }
-            if (j == 0) {
-              float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
-              if (v0 != 0.f) atomicAdd(tr, v0);
-              if (v1 != 0.f) atomicAdd(tr + 1, v1);
-            }
+            if (j == 0) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr, v0, v1, res <= MAP_MAX_RES);
           } else if (valid) {
-            float* tr = a.g_table_rad + ((size_t)lev * Tr + rr) * 2;
-            if (v0 != 0.f) atomicAdd(tr, v0);
-            if (v1 != 0.f) atomicAdd(tr + 1, v1);
+            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr, v0, v1, res <= MAP_MAX_RES);
           }
+        }
+      }
+    }
+  }
+  if constexpr (RAY) {
+    __syncthreads();
+    if (a.g_table_rad) {
+      for (int k = threadIdx.x; k < MAP_SLOTS; k += BWD_NT) {
+        const uint32_t key = map_key[k];
+        if (key != MAP_EMPTY) {
+          const float2 v = map_val[k];
+          if (v.x != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2, v.x);
+          if (v.y != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2 + 1, v.y);
         }
       }
     }
