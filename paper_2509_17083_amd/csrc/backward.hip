@@ -351,7 +351,8 @@ __device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py
 
 constexpr int MAP_SLOTS = 2048;
 constexpr uint32_t MAP_EMPTY = 0xFFFFFFFFu;
-constexpr int MAP_MAX_RES = 410;   // levels up to this resolution use the workgroup map
+constexpr int MAP_MAX_RES = 182;   // levels up to this resolution use the workgroup map
+constexpr int MAP_SEG_RES = 1383;  // levels up to this resolution pre-reduce runs of equal rows
 
 // Add (v0, v1) to table row `row` of level `lev`: through the workgroup map
 // when `use_map` (linear probing, at most 8 slots), else (or when the probe
@@ -585,19 +586,28 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
           const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
           const uint32_t rr0 = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn,
                                           side, a.grid.mask_rad);
-          const uint32_t key0 = __shfl(rr0, lane & 48, 64);
-          const uint32_t rr = valid ? rr0 : key0;
-          float v0 = wc * fr0, v1 = wc * fr1;
-          const uint64_t same = __ballot(rr == key0) & gmask;
-          if (same == gmask) {
+          const float v0 = valid ? wc * fr0 : 0.f, v1 = valid ? wc * fr1 : 0.f;
+          if (res <= MAP_SEG_RES) {
+            // runs of equal rows among the 16 pixels: sum each run in
+            // registers (up to 3 runs), one add per run
+            uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f) & gmask;
+#pragma unroll 1
+            for (int it = 0; it < 3 && pending; ++it) {
+              const int lead = __ffsll((long long)pending) - 1;
+              const uint32_t keyL = __shfl(rr0, lead, 64);
+              const bool mine = ((pending >> lane) & 1ull) && rr0 == keyL;
+              float s0 = mine ? v0 : 0.f, s1 = mine ? v1 : 0.f;
 #pragma unroll
-            for (int off = 8; off > 0; off >>= 1) {
-              v0 += __shfl_xor(v0, off, 64);
-              v1 += __shfl_xor(v1, off, 64);
+              for (int off = 8; off > 0; off >>= 1) {
+                s0 += __shfl_xor(s0, off, 64);
+                s1 += __shfl_xor(s1, off, 64);
+              }
+              if (lane == lead) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, keyL, s0, s1, res <= MAP_MAX_RES);
+              pending &= ~(__ballot(mine) & gmask);
             }
-            if (j == 0) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr, v0, v1, res <= MAP_MAX_RES);
-          } else if (valid) {
-            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr, v0, v1, res <= MAP_MAX_RES);
+            if ((pending >> lane) & 1ull) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr0, v0, v1, false);
+          } else {
+            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr0, v0, v1, false);
           }
         }
       }
