@@ -192,6 +192,14 @@ def main():
     st_render = stages(ev_r, fwd_keys)
     print(f"[bench] render {ms_render:.3f} ms/frame; stages {st_render}", file=sys.stderr, flush=True)
 
+    # precision variant: float16 tables, bfloat16 decoder operands
+    dv = ds.with_precision(P.F16, P.BF16)
+    ms_render_v, ev_v, _ = timed(lambda ev: P.render(dv, cams, P.RENDER, ws=ws, events=ev), args.steps)
+    st_render_v = stages(ev_v, fwd_keys)
+    print(f"[bench] render (f16 tables, bf16 MLP) {ms_render_v:.3f} ms/frame; stages {st_render_v}",
+          file=sys.stderr, flush=True)
+    del dv
+
     # dominant forward kernel: the field query (gather-bound); algorithmic bytes
     # per surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
     # + explicit parameters read (56 B) + aggregated properties written (44 B)
@@ -216,6 +224,9 @@ def main():
            "render_fps": round(1000.0 / ms_render, 2),
            "stage_ms_train": {k: round(v, 4) for k, v in st_train.items()},
            "stage_ms_render": {k: round(v, 4) for k, v in st_render.items()},
+           "variant_f16_bf16": {"render_ms": round(ms_render_v, 4), "render_fps": round(1000.0 / ms_render_v, 2),
+                                "stage_ms_render": {k: round(v, 4) for k, v in st_render_v.items()},
+                                "train_step_ms": None},
            "tile_entries": st.n_entries,
            "roofline": roof}
     if not args.no_cpu_baseline:

@@ -90,13 +90,16 @@ hyrf_status check_fields(const hyrf_fields* f) {
   REQ(f->n_hidden == 1 || f->n_hidden == 2, "n_hidden must be 1 or 2");
   REQ(f->bg_radius > 0.f, "bg_radius must be positive");
   for (int d = 0; d < 3; ++d) REQ(f->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
-  if (!(f->table_dtype == HYRF_F32))
-    return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported", f->table_dtype);
-  if (!(f->mlp_dtype == HYRF_F32))
-    return fail(HYRF_ERR_UNSUPPORTED, "mlp dtype %d not supported", f->mlp_dtype);
+  if (!(f->table_dtype == HYRF_F32 || f->table_dtype == HYRF_F16))
+    return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported (F32 or F16)", f->table_dtype);
+  if (!(f->mlp_dtype == HYRF_F32 || f->mlp_dtype == HYRF_BF16))
+    return fail(HYRF_ERR_UNSUPPORTED, "mlp dtype %d not supported (F32 or BF16)", f->mlp_dtype);
   if (!shape_supported(f->levels, f->hidden, f->n_hidden))
     return fail(HYRF_ERR_UNSUPPORTED, "no kernel for levels=%d hidden=%d n_hidden=%d "
                 "(built: 16/64/2, 16/64/1, 8/32/1, 8/64/2)", f->levels, f->hidden, f->n_hidden);
+  if (!precision_supported(f->levels, f->hidden, f->n_hidden, f->table_dtype == HYRF_F16, f->mlp_dtype == HYRF_BF16))
+    return fail(HYRF_ERR_UNSUPPORTED, "float16 tables / bfloat16 decoders are built for levels=16 hidden=64 "
+                "n_hidden=2 only");
   return HYRF_OK;
 }
 
@@ -166,8 +169,8 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     QueryArgs a{};
     a.grid = make_grid(fields);
     a.cams = cc;
-    a.table_geo = (const float*)fields->table_geo;
-    a.table_rad = (const float*)fields->table_rad;
+    a.table_geo = fields->table_geo;
+    a.table_rad = fields->table_rad;
     a.w_geo = fields->mlp_geo;
     a.w_col = fields->mlp_col;
     a.n = g->n;
@@ -185,7 +188,8 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     a.feat_geo = out->feat_geo;
     a.feat_rad = out->feat_rad;
     a.dbg = out->dbg_index;
-    launch_query(fields->levels, fields->hidden, fields->n_hidden, a, g->n, st);
+    launch_query(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype == HYRF_F16,
+                 fields->mlp_dtype == HYRF_BF16, a, g->n, st);
   }
   return check_launch();
 }
@@ -308,7 +312,7 @@ hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const ui
     BgArgs b{};
     b.grid = make_grid(fields);
     b.cams = make_cams(cams, n_views);
-    b.table_rad = (const float*)fields->table_rad;
+    b.table_rad = fields->table_rad;
     b.w_col = fields->mlp_col;
     b.W = W;
     b.H = H;
@@ -317,7 +321,8 @@ hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const ui
     b.T = out_T;
     b.out_rgb = out_rgb;
     b.bg_save = mode == HYRF_TRAIN ? out_bg : nullptr;
-    launch_bg(fields->levels, fields->hidden, fields->n_hidden, b, n_views * W * H, st);
+    launch_bg(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype == HYRF_F16,
+              fields->mlp_dtype == HYRF_BF16, b, n_views * W * H, st);
   }
   return check_launch();
 }
@@ -375,6 +380,8 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   if ((s = check_fields(fields)) != HYRF_OK) return s;
   if ((s = check_gauss(g)) != HYRF_OK) return s;
   if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  if (fields->table_dtype != HYRF_F32 || fields->mlp_dtype != HYRF_F32)
+    return fail(HYRF_ERR_UNSUPPORTED, "the backward of float16-table / bfloat16-decoder fields is not built");
   REQ(saved && saved->query && saved->splats, "saved forward state is incomplete");
   const hyrf_query_out* q = saved->query;
   const hyrf_splats* sp = saved->splats;

@@ -484,7 +484,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       double ps[3], d[3];
       sphere_point_f64(a.cams.c[v_r], xx, yy, (double)a.grid.bg_radius, ps, d);
       contract_f64(a.grid, ps[0], ps[1], ps[2], x);
-      gather_lane<Sh::L, false>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
+      gather_lane<Sh::L, false, float>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
       const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
       pxf = (float)(d[0] / dn); pyf = (float)(d[1] / dn); pzf = (float)(d[2] / dn);
       if (!valid) {

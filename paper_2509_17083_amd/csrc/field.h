@@ -22,6 +22,7 @@
 namespace hyrf {
 
 constexpr int pad4(int x) { return (x + 3) & ~3; }
+constexpr int pad8(int x) { return (x + 7) & ~7; }
 
 template <int L_, int HID_, int NH_>
 struct Shape {
@@ -32,6 +33,11 @@ struct Shape {
   static constexpr int S_GEO1 = pad4(L / 2);
   static constexpr int S_COL1 = pad4(L / 2 + 6);
   static constexpr int S_HID = HID / 4;
+  // bf16 path: 8 lane inputs per k-step
+  static constexpr int S_GEO1_8 = pad8(L / 2);
+  static constexpr int S_COL1_8 = pad8(L / 2 + 6);
+  static constexpr int WB16_GEO = NT * S_GEO1_8 * 64 + (NH - 1) * NT * S_HID * 64 + S_HID * 64;
+  static constexpr int WB16_COL = NT * S_COL1_8 * 64 + (NH - 1) * NT * S_HID * 64 + S_HID * 64;
   static constexpr int IN_GEO = 2 * L;
   static constexpr int IN_COL = 2 * L + 6 * HYRF_PE_OCTAVES;
   // LDS floats per MLP
@@ -143,11 +149,98 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ Wlds, cons
   out = o[0];
 }
 
+
+// ---------------------------------------------------------------------------
+// BF16 operands (v_mfma_f32_16x16x32_bf16, FP32 accumulate).  Same k order
+// as the FP32 path, 8 consecutive lane inputs per k-step: per layer
+// [out_tile][s/8][lane][8] bf16 (one 16-byte A operand per lane and step).
+template <class Sh>
+__device__ void permute_mlp_fwd_bf16(__bf16* dst, const float* __restrict__ W, bool colour, int tid, int stride) {
+  const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
+  const int in1 = colour ? Sh::IN_COL : Sh::IN_GEO;
+  const int S1 = colour ? Sh::S_COL1_8 : Sh::S_GEO1_8;
+  int dst_off = 0, g_off = 0;
+  for (int layer = 0; layer <= Sh::NH; ++layer) {
+    const bool first = layer == 0;
+    const bool last = layer == Sh::NH;
+    const int S = first ? S1 : Sh::S_HID;
+    const int NTo = last ? 1 : Sh::NT;
+    const int rows = last ? n_out : Sh::HID;
+    const int in = first ? in1 : Sh::HID;
+    const int cnt = NTo * S * 64;
+    for (int e = tid; e < cnt; e += stride) {
+      const int s8 = e & 7;
+      const int lane = (e >> 3) & 63;
+      const int rest = e >> 9;                 // ot * (S/8) + q
+      const int q = rest % (S / 8);
+      const int ot = rest / (S / 8);
+      const int s = q * 8 + s8;
+      const int g = lane >> 4;
+      const int row = ot * 16 + (lane & 15);
+      const int col = first ? first_layer_col<Sh::L>(s, g, colour) : (16 * (s >> 2) + 4 * g + (s & 3));
+      float val = 0.f;
+      if (row < rows && col >= 0 && col < in) val = W[g_off + row * in + col];
+      dst[dst_off + e] = (__bf16)val;
+    }
+    dst_off += cnt;
+    g_off += rows * in;
+  }
+}
+
+template <int NTO, int S>
+__device__ __forceinline__ void mfma_layer_bf16(const __bf16* __restrict__ Wl, const float (&x)[S],
+                                                v4f (&acc)[NTO], int lane) {
+  static_assert(S % 8 == 0, "bf16 layer width");
+#pragma unroll
+  for (int ot = 0; ot < NTO; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < S / 8; ++q) {
+    v8bf b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) b[e] = (__bf16)x[8 * q + e];
+#pragma unroll
+    for (int ot = 0; ot < NTO; ++ot) {
+      const v8bf w = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + q) * 64 + lane) * 8);
+      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, acc[ot], 0, 0, 0);
+    }
+    asm volatile("" ::: "memory");
+  }
+}
+
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward_bf16(const __bf16* __restrict__ Wlds, const float (&x1)[S1],
+                                                 v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer_bf16<Sh::NT, S1>(Wlds, x1, acc, lane);
+  const __bf16* W = Wlds + Sh::NT * S1 * 64;
+  float h[Sh::S_HID];
+  relu_to_inputs<Sh::NT>(acc, h);
+#pragma unroll
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, h, acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(acc, h);
+  }
+  v4f o[1];
+  mfma_layer_bf16<1, Sh::S_HID>(W, h, o, lane);
+  out = o[0];
+}
+
+// Table entry loads: FP32 pairs or FP16 pairs widened to FP32.
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 load_entry(const float* t, size_t i) {
+  return *reinterpret_cast<const float2*>(t + i * 2);
+}
+__device__ __forceinline__ float2 load_entry(const _Float16* t, size_t i) {
+  const h2_t v = *reinterpret_cast<const h2_t*>(t + i * 2);
+  return make_float2((float)v.x, (float)v.y);
+}
+
 // Gather this lane's levels from both tables at contracted position x.
 // fg / fr: lane features (level g + 4k, feature f) at index 2k + f.
-template <int L, bool GEO>
+template <int L, bool GEO, class TT>
 __device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], int g,
-                                            const float* __restrict__ tg, const float* __restrict__ tr,
+                                            const TT* __restrict__ tg, const TT* __restrict__ tr,
                                             float (&fg)[L / 2], float (&fr)[L / 2],
                                             uint32_t* dbg_geo, uint32_t* dbg_rad) {
   const uint32_t Tg = gp.mask_geo + 1u, Tr = gp.mask_rad + 1u;
@@ -173,11 +266,11 @@ __device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], 
       const float wz = ((c >> 2) & 1) ? w[2] : 1.f - w[2];
       wc[c] = (wx * wy) * wz;
       const uint32_t rr = corner_row(cx, cy, cz, dr, side, gp.mask_rad);
-      vr[c] = *reinterpret_cast<const float2*>(tr + ((size_t)lev * Tr + rr) * 2);
+      vr[c] = load_entry(tr, (size_t)lev * Tr + rr);
       if (dbg_rad) dbg_rad[lev * 8 + c] = rr;
       if (GEO) {
         const uint32_t rg = corner_row(cx, cy, cz, dg, side, gp.mask_geo);
-        vg[c] = *reinterpret_cast<const float2*>(tg + ((size_t)lev * Tg + rg) * 2);
+        vg[c] = load_entry(tg, (size_t)lev * Tg + rg);
         if (dbg_geo) dbg_geo[lev * 8 + c] = rg;
       }
     }

@@ -10,8 +10,8 @@ constexpr int QUERY_MAX_BLOCKS = 512;  // 2 workgroups per CU on 256 CUs (persis
 struct QueryArgs {
   GridP grid;
   Cams cams;
-  const float* table_geo;
-  const float* table_rad;
+  const void* table_geo;       // float32 or float16 pairs
+  const void* table_rad;
   const float* w_geo;
   const float* w_col;
   int n;                      // Gaussian count (stride of the planar arrays)
@@ -34,7 +34,7 @@ struct QueryArgs {
 struct BgArgs {
   GridP grid;
   Cams cams;
-  const float* table_rad;
+  const void* table_rad;
   const float* w_col;
   int W, H;
   const uint32_t* list;        // pixel ids v*H*W + y*W + x, or NULL = every pixel
@@ -45,8 +45,10 @@ struct BgArgs {
 };
 
 bool shape_supported(int L, int hid, int nh);
-void launch_query(int L, int hid, int nh, const QueryArgs& a, int n_cap, hipStream_t st);
-void launch_bg(int L, int hid, int nh, const BgArgs& a, int n_cap, hipStream_t st);
+// f16: tables in float16; bf: decoder operands in bfloat16 (FP32 accumulate).
+bool precision_supported(int L, int hid, int nh, bool f16, bool bf);
+void launch_query(int L, int hid, int nh, bool f16, bool bf, const QueryArgs& a, int n_cap, hipStream_t st);
+void launch_bg(int L, int hid, int nh, bool f16, bool bf, const BgArgs& a, int n_cap, hipStream_t st);
 void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
                  uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st);
 

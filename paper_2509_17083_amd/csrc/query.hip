@@ -5,6 +5,8 @@
 #include "kernels.h"
 #include "query.h"
 
+#include <type_traits>
+
 namespace hyrf {
 
 // ---------------------------------------------------------------- pre-cull
@@ -31,13 +33,35 @@ __global__ __launch_bounds__(256) void k_cull_write(const uint32_t* __restrict__
 }
 
 // ---------------------------------------------------------------- field query
-template <class Sh>
+// Weight storage of one MLP in LDS: permuted FP32 A operands, or BF16.
+template <class Sh, bool BF>
+struct MlpLds {
+  using T = typename std::conditional<BF, __bf16, float>::type;
+  static constexpr int GEO = BF ? Sh::WB16_GEO : Sh::W_GEO;
+  static constexpr int COL = BF ? Sh::WB16_COL : Sh::W_COL;
+  static constexpr int SG = BF ? Sh::S_GEO1_8 : Sh::S_GEO1;   // first-layer k-steps (lane inputs)
+  static constexpr int SC = BF ? Sh::S_COL1_8 : Sh::S_COL1;
+  static __device__ void load(T* dst, const float* W, bool colour) {
+    if constexpr (BF) permute_mlp_fwd_bf16<Sh>(dst, W, colour, threadIdx.x, blockDim.x);
+    else permute_mlp_fwd<Sh>(dst, W, colour, threadIdx.x, blockDim.x);
+  }
+  template <int S1>
+  static __device__ void run(const T* W, const float (&x)[S1], v4f& out, int lane) {
+    if constexpr (BF) mlp_forward_bf16<Sh, S1>(W, x, out, lane);
+    else mlp_forward<Sh, S1>(W, x, out, lane);
+  }
+};
+
+template <class Sh, class TT, bool BF>
 __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
-  __shared__ __attribute__((aligned(16))) float w_geo[Sh::W_GEO];
-  __shared__ __attribute__((aligned(16))) float w_col[Sh::W_COL];
-  load_mlp_lds<Sh>(w_geo, a.w_geo, false);
-  load_mlp_lds<Sh>(w_col, a.w_col, true);
+  using M = MlpLds<Sh, BF>;
+  __shared__ __attribute__((aligned(16))) typename M::T w_geo[M::GEO];
+  __shared__ __attribute__((aligned(16))) typename M::T w_col[M::COL];
+  M::load(w_geo, a.w_geo, false);
+  M::load(w_col, a.w_col, true);
   __syncthreads();
+  const TT* table_geo = reinterpret_cast<const TT*>(a.table_geo);
+  const TT* table_rad = reinterpret_cast<const TT*>(a.table_rad);
 
   const int lane = lane_id();
   const int j = lane & 15, g = lane >> 4;
@@ -61,7 +85,7 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       dg = a.dbg + (size_t)slot * 2 * Sh::L * 8;
       dr = dg + Sh::L * 8;
     }
-    gather_lane<Sh::L, true>(a.grid, x, g, a.table_geo, a.table_rad, fg, fr, dg, dr);
+    gather_lane<Sh::L, true, TT>(a.grid, x, g, table_geo, table_rad, fg, fr, dg, dr);
     if (a.feat_geo && valid) {
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
@@ -71,11 +95,11 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       }
     }
     // geometry decoder
-    float xg[Sh::S_GEO1];
+    float xg[M::SG];
 #pragma unroll
-    for (int s = 0; s < Sh::S_GEO1; ++s) xg[s] = s < Sh::FPL ? fg[s] : 0.f;
+    for (int s = 0; s < M::SG; ++s) xg[s] = s < Sh::FPL ? fg[s] : 0.f;
     v4f og;
-    mlp_forward<Sh, Sh::S_GEO1>(w_geo, xg, og, lane);
+    M::template run<M::SG>(w_geo, xg, og, lane);
     // rows 4..7 (rotation) live in lane group 1: bring them to group 0
     float rn[4];
 #pragma unroll
@@ -101,12 +125,12 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       dx *= inv; dy *= inv; dz *= inv;
       float pe[6];
       pe_lane(g, dx, dy, dz, pe);
-      float xc[Sh::S_COL1];
+      float xc[M::SC];
 #pragma unroll
-      for (int s = 0; s < Sh::S_COL1; ++s)
+      for (int s = 0; s < M::SC; ++s)
         xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
       v4f oc4;
-      mlp_forward<Sh, Sh::S_COL1>(w_col, xc, oc4, lane);
+      M::template run<M::SC>(w_col, xc, oc4, lane);
       if (g == 0 && valid) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
@@ -117,11 +141,13 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
 }
 
 // ---------------------------------------------------------------- background
-template <class Sh>
+template <class Sh, class TT, bool BF>
 __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
-  __shared__ __attribute__((aligned(16))) float w_col[Sh::W_COL];
-  load_mlp_lds<Sh>(w_col, a.w_col, true);
+  using M = MlpLds<Sh, BF>;
+  __shared__ __attribute__((aligned(16))) typename M::T w_col[M::COL];
+  M::load(w_col, a.w_col, true);
   __syncthreads();
+  const TT* table_rad = reinterpret_cast<const TT*>(a.table_rad);
   const int lane = lane_id();
   const int j = lane & 15, g = lane >> 4;
   const int HW = a.W * a.H;
@@ -142,16 +168,16 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
     double x[3];
     contract_f64(a.grid, ps[0], ps[1], ps[2], x);
     float fg[Sh::FPL], fr[Sh::FPL];
-    gather_lane<Sh::L, false>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
+    gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, table_rad, fg, fr, nullptr, nullptr);
     const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
     float pe[6];
     pe_lane(g, (float)(d[0] / dn), (float)(d[1] / dn), (float)(d[2] / dn), pe);
-    float xc[Sh::S_COL1];
+    float xc[M::SC];
 #pragma unroll
-    for (int s = 0; s < Sh::S_COL1; ++s)
+    for (int s = 0; s < M::SC; ++s)
       xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
     v4f o;
-    mlp_forward<Sh, Sh::S_COL1>(w_col, xc, o, lane);
+    M::template run<M::SC>(w_col, xc, o, lane);
     if (g == 0 && valid) {
       const float T = a.T[pix];
 #pragma unroll
@@ -166,22 +192,22 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
 }
 
 // ---------------------------------------------------------------- launchers
-template <class Sh>
+template <class Sh, class TT, bool BF>
 static void launch_query_t(const QueryArgs& a, int n_cap, hipStream_t st) {
   int groups = (n_cap + 15) / 16;
   int blocks = (groups + QUERY_NT / 64 - 1) / (QUERY_NT / 64);
   if (blocks > QUERY_MAX_BLOCKS) blocks = QUERY_MAX_BLOCKS;
   if (blocks < 1) blocks = 1;
-  k_field_query<Sh><<<blocks, QUERY_NT, 0, st>>>(a);
+  k_field_query<Sh, TT, BF><<<blocks, QUERY_NT, 0, st>>>(a);
 }
 
-template <class Sh>
+template <class Sh, class TT, bool BF>
 static void launch_bg_t(const BgArgs& a, int n_cap, hipStream_t st) {
   int groups = (n_cap + 15) / 16;
   int blocks = (groups + QUERY_NT / 64 - 1) / (QUERY_NT / 64);
   if (blocks > QUERY_MAX_BLOCKS) blocks = QUERY_MAX_BLOCKS;
   if (blocks < 1) blocks = 1;
-  k_bg_query<Sh><<<blocks, QUERY_NT, 0, st>>>(a);
+  k_bg_query<Sh, TT, BF><<<blocks, QUERY_NT, 0, st>>>(a);
 }
 
 bool shape_supported(int L, int hid, int nh) {
@@ -191,16 +217,32 @@ bool shape_supported(int L, int hid, int nh) {
 
 #define HYRF_SHAPES(X) X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
 
-void launch_query(int L, int hid, int nh, const QueryArgs& a, int n_cap, hipStream_t st) {
-#define X(l, h, k) if (L == l && hid == h && nh == k) return launch_query_t<Shape<l, h, k>>(a, n_cap, st);
-  HYRF_SHAPES(X)
-#undef X
+#define HYRF_DISPATCH(FN, ...)                                                                  \
+  do {                                                                                          \
+    if (L == 16 && hid == 64 && nh == 2) {                                                      \
+      using Sh = Shape<16, 64, 2>;                                                              \
+      if (!f16 && !bf) return FN<Sh, float, false>(__VA_ARGS__);                                \
+      if (!f16 && bf) return FN<Sh, float, true>(__VA_ARGS__);                                  \
+      if (f16 && !bf) return FN<Sh, _Float16, false>(__VA_ARGS__);                              \
+      return FN<Sh, _Float16, true>(__VA_ARGS__);                                               \
+    }                                                                                           \
+    if (f16 || bf) return;                                                                      \
+    if (L == 8 && hid == 32 && nh == 1) return FN<Shape<8, 32, 1>, float, false>(__VA_ARGS__);  \
+    if (L == 16 && hid == 64 && nh == 1) return FN<Shape<16, 64, 1>, float, false>(__VA_ARGS__); \
+    if (L == 8 && hid == 64 && nh == 2) return FN<Shape<8, 64, 2>, float, false>(__VA_ARGS__);  \
+  } while (0)
+
+void launch_query(int L, int hid, int nh, bool f16, bool bf, const QueryArgs& a, int n_cap, hipStream_t st) {
+  HYRF_DISPATCH(launch_query_t, a, n_cap, st);
 }
 
-void launch_bg(int L, int hid, int nh, const BgArgs& a, int n_cap, hipStream_t st) {
-#define X(l, h, k) if (L == l && hid == h && nh == k) return launch_bg_t<Shape<l, h, k>>(a, n_cap, st);
-  HYRF_SHAPES(X)
-#undef X
+void launch_bg(int L, int hid, int nh, bool f16, bool bf, const BgArgs& a, int n_cap, hipStream_t st) {
+  HYRF_DISPATCH(launch_bg_t, a, n_cap, st);
+}
+
+bool precision_supported(int L, int hid, int nh, bool f16, bool bf) {
+  if (!f16 && !bf) return shape_supported(L, hid, nh);
+  return L == 16 && hid == 64 && nh == 2;
 }
 
 void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,

@@ -75,6 +75,15 @@ class DeviceScene:
             aabb_inv_half=tuple(float(x) for x in s.aabb_inv_half),
             bg_radius=float(s.bg_radius), tau_T=float(s.tau_T))
 
+    def with_precision(self, table_dtype: int = F16, mlp_dtype: int = BF16) -> "DeviceScene":
+        """The same scene with float16 tables and/or bfloat16 decoder operands
+        (weights stay float32 in memory; the kernels round them on load)."""
+        import dataclasses
+        tt = torch.float16 if table_dtype == F16 else torch.float32
+        return dataclasses.replace(self, table_geo=self.table_geo.to(tt).contiguous(),
+                                   table_rad=self.table_rad.to(tt).contiguous(),
+                                   table_dtype=table_dtype, mlp_dtype=mlp_dtype)
+
     def c_fields(self) -> A.hyrf_fields:
         f = A.hyrf_fields()
         f.levels, f.features = self.levels, 2

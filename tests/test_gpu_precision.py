@@ -1,0 +1,75 @@
+"""Precision variant: float16 hash tables and bfloat16 decoder operands on
+MFMA with float32 accumulation; projection, conics and blending in float32.
+Reported against the FP64 oracle; the bar is the PSNR of the variant against
+a target image staying within 0.05 dB of the FP32 path's."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import hyrf_inputs as hi
+from oracle import hyrf_oracle as O
+from _hyrf_testutil import device_scene, make, oracle_view
+
+pytestmark = pytest.mark.gpu
+
+
+def _P():
+    import paper_2509_17083_amd as P
+    return P
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    _P()._abi.load()
+
+
+def psnr(a, b):
+    mse = float(np.mean((np.asarray(a, np.float64) - np.asarray(b, np.float64)) ** 2))
+    return 10 * math.log10(1.0 / mse) if mse > 0 else float("inf")
+
+
+OVER = {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 16}
+
+
+@pytest.mark.parametrize("mode", [O.TRAIN, O.RENDER])
+def test_variant_psnr_within_005db_of_fp32(mode):
+    P = _P()
+    cfg, scene, cams = make("c100k", table_init=1.0, **OVER)
+    scene.scale_e += np.float32(1.0)
+    cam = cams[0]
+    H, W = cam.height, cam.width
+    ref = oracle_view(scene, cam, mode, stats=False)["rgb"].numpy().T.reshape(3, H, W)
+    # target: the oracle's render of a second seeded scene of the same kind
+    _, tscene, _ = make("c100k", seed=2001, table_init=1.0, **OVER)
+    tscene.scale_e += np.float32(1.0)
+    tgt = oracle_view(tscene, cam, mode, stats=False)["rgb"].numpy().T.reshape(3, H, W)
+    ds = device_scene(scene)
+    i32 = P.render(ds, cams, mode).image[0].cpu().numpy()
+    out = {}
+    for name, td, md in (("f16-table", P.F16, P.F32), ("bf16-mlp", P.F32, P.BF16), ("f16+bf16", P.F16, P.BF16)):
+        iv = P.render(ds.with_precision(td, md), cams, mode).image[0].cpu().numpy()
+        out[name] = dict(psnr_vs_fp64=psnr(iv, ref), dpsnr_target=psnr(iv, tgt) - psnr(i32, tgt),
+                         max_abs=float(np.abs(iv - ref).max()))
+    torch.cuda.synchronize()
+    print("fp32: psnr_vs_fp64 %.1f dB; target psnr %.3f dB" % (psnr(i32, ref), psnr(i32, tgt)), flush=True)
+    for k, v in out.items():
+        print(k, {a: round(b, 4) for a, b in v.items()}, flush=True)
+    assert psnr(i32, ref) > 90
+    for k, v in out.items():
+        assert abs(v["dpsnr_target"]) <= 0.05, (k, v)
+        assert v["psnr_vs_fp64"] > 40, (k, v)
+
+
+def test_variant_backward_is_reported_unsupported():
+    P = _P()
+    from paper_2509_17083_amd import _abi as A
+    cfg, scene, cams = make("c100k", table_init=1.0, **OVER)
+    ds = device_scene(scene).with_precision(P.F16, P.BF16)
+    st = P.render(ds, cams, P.TRAIN)
+    with pytest.raises(A.HyrfError) as e:
+        P.render_backward(ds, cams, st, torch.zeros_like(st.image))
+    assert e.value.status == A.HYRF_ERR_UNSUPPORTED
