@@ -236,7 +236,8 @@ size_t hyrf_query_workspace_bytes(int32_t n);
 size_t hyrf_bin_sort_workspace_bytes(int32_t n_views, int32_t n_max, int64_t capacity,
                                      int32_t width, int32_t height);
 size_t hyrf_composite_workspace_bytes(int32_t n_views, int32_t width, int32_t height);
-size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max);
+size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max,
+                                     int32_t width, int32_t height);
 size_t hyrf_l1_workspace_bytes(int64_t n);
 /* Message of the last failed call on this thread ("" if none). */
 const char* hyrf_last_error(void);

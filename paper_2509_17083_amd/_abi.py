@@ -74,7 +74,8 @@ EXPORTS = {
     "hyrf_query_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hyrf_bin_sort_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]),
     "hyrf_composite_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
-    "hyrf_backward_workspace_bytes": (C.c_size_t, [C.POINTER(hyrf_fields), C.c_int32, C.c_int32]),
+    "hyrf_backward_workspace_bytes": (C.c_size_t, [C.POINTER(hyrf_fields), C.c_int32, C.c_int32, C.c_int32,
+                                                   C.c_int32]),
     "hyrf_l1_workspace_bytes": (C.c_size_t, [C.c_int64]),
     "hyrf_last_error": (C.c_char_p, []),
     "hyrf_version": (C.c_char_p, []),

@@ -62,6 +62,7 @@ struct FieldBwdArgs {
   const float* dcol;
   float* dfeat_geo;      // [n][2L] feature gradients handed to the grid adjoint
   float* dfeat_rad;
+  float* dfeat_bg;       // [V*H*W][2L] background feature gradients
   float* g_pos;
   float* g_rot_e;
   float* g_table_geo;
@@ -85,6 +86,14 @@ struct GridBwdArgs {
   const float* dfeat_rad;
   float* g_pos;
   float* g_table_geo;
+  float* g_table_rad;
+};
+
+struct BgGridArgs {
+  GridP grid;
+  Cams cams;
+  int W, H;
+  const float* dfeat_bg;
   float* g_table_rad;
 };
 

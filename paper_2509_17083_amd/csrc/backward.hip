@@ -350,6 +350,7 @@ __device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py
 }
 
 constexpr int MAP_SLOTS = 2048;
+constexpr int BG_GRID_BLOCKS = 1024;   // persistent: 4 workgroups per CU, each a contiguous pixel band
 constexpr uint32_t MAP_EMPTY = 0xFFFFFFFFu;
 constexpr int MAP_MAX_RES = 182;   // levels up to this resolution use the workgroup map
 constexpr int MAP_SEG_RES = 1383;  // levels up to this resolution pre-reduce runs of equal rows
@@ -385,20 +386,9 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   constexpr int ACC = B::ACC;
   __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
   __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
-  // background mode: workgroup-private accumulation of the coarse levels'
-  // table gradients (open addressing on key = level * T + row)
-  __shared__ uint32_t map_key[RAY ? MAP_SLOTS : 1];
-  __shared__ float2 map_val[RAY ? MAP_SLOTS : 1];
   const int lane = lane_id();
   const int j = lane & 15, g = lane >> 4;
   const int w = threadIdx.x / 64;
-  if constexpr (RAY) {
-    for (int k = threadIdx.x; k < MAP_SLOTS; k += BWD_NT) {
-      map_key[k] = MAP_EMPTY;
-      map_val[k] = make_float2(0.f, 0.f);
-    }
-    __syncthreads();
-  }
   v4f accW[ACC];
 #pragma unroll
   for (int k = 0; k < ACC; ++k) accW[k] = v4f{0.f, 0.f, 0.f, 0.f};
@@ -564,65 +554,12 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       if (valid && g == 0 && a.g_pos)
 #pragma unroll
         for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k];
-    } else if (a.g_table_rad) {
-      // Background points: scatter-add into the radiance table only.  The 16
-      // pixels of a lane group are consecutive in a row, so at the coarse
-      // levels they usually share a cell: when all 16 rows of a corner agree,
-      // the group sums in registers and issues one atomic instead of 16.
-      const uint64_t gmask = 0xFFFFull << (16 * g);
+    } else if (valid) {
+      // background points: feature gradients handed to the background grid adjoint
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
-        const int res = a.grid.res[lev];
-        int ci[3];
-        float wv[3];
-        grid_cell(x, res, ci, wv);
-        const uint32_t side = (uint32_t)res + 1u;
-        const bool drn = (a.grid.dense_rad >> lev) & 1u;
-        const float fr0 = valid ? dfr[2 * k] : 0.f, fr1 = valid ? dfr[2 * k + 1] : 0.f;
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-          const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
-          const uint32_t rr0 = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn,
-                                          side, a.grid.mask_rad);
-          const float v0 = valid ? wc * fr0 : 0.f, v1 = valid ? wc * fr1 : 0.f;
-          if (res <= MAP_SEG_RES) {
-            // runs of equal rows among the 16 pixels: sum each run in
-            // registers (up to 3 runs), one add per run
-            uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f) & gmask;
-#pragma unroll 1
-            for (int it = 0; it < 3 && pending; ++it) {
-              const int lead = __ffsll((long long)pending) - 1;
-              const uint32_t keyL = __shfl(rr0, lead, 64);
-              const bool mine = ((pending >> lane) & 1ull) && rr0 == keyL;
-              float s0 = mine ? v0 : 0.f, s1 = mine ? v1 : 0.f;
-#pragma unroll
-              for (int off = 8; off > 0; off >>= 1) {
-                s0 += __shfl_xor(s0, off, 64);
-                s1 += __shfl_xor(s1, off, 64);
-              }
-              if (lane == lead) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, keyL, s0, s1, res <= MAP_MAX_RES);
-              pending &= ~(__ballot(mine) & gmask);
-            }
-            if ((pending >> lane) & 1ull) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr0, v0, v1, false);
-          } else {
-            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, rr0, v0, v1, false);
-          }
-        }
-      }
-    }
-  }
-  if constexpr (RAY) {
-    __syncthreads();
-    if (a.g_table_rad) {
-      for (int k = threadIdx.x; k < MAP_SLOTS; k += BWD_NT) {
-        const uint32_t key = map_key[k];
-        if (key != MAP_EMPTY) {
-          const float2 v = map_val[k];
-          if (v.x != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2, v.x);
-          if (v.y != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2 + 1, v.y);
-        }
+        *reinterpret_cast<float2*>(a.dfeat_bg + (size_t)pix * 2 * Sh::L + 2 * lev) = make_float2(dfr[2 * k], dfr[2 * k + 1]);
       }
     }
   }
@@ -705,6 +642,91 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   }
 }
 
+// Hash-grid adjoint of the background points (radiance table only; the
+// sphere points do not depend on parameters).  One lane per pixel, 64
+// consecutive pixels of a row per wave, all levels per lane.  Equal rows
+// among the wave's pixels are summed in registers first (runs of consecutive
+// pixels share the coarse cells); the coarsest levels then go through a
+// workgroup-private map that each persistent workgroup flushes once, the
+// finer ones straight to global atomics.
+__global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
+  __shared__ uint32_t map_key[MAP_SLOTS];
+  __shared__ float2 map_val[MAP_SLOTS];
+  for (int k = threadIdx.x; k < MAP_SLOTS; k += 256) {
+    map_key[k] = MAP_EMPTY;
+    map_val[k] = make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  const int lane = lane_id();
+  const int HW = a.W * a.H;
+  const int64_t total = (int64_t)a.cams.V * HW;
+  const int64_t chunks = (total + 255) / 256;
+  const int64_t per_blk = (chunks + gridDim.x - 1) / gridDim.x;
+  const int64_t c0 = (int64_t)blockIdx.x * per_blk;
+  const int64_t c1 = min(chunks, c0 + per_blk);
+  const uint32_t Tr = a.grid.mask_rad + 1u;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    const int64_t pix64 = ch * 256 + threadIdx.x;
+    const bool valid = pix64 < total;
+    const int pix = valid ? (int)pix64 : 0;
+    const int v = pix / HW;
+    const int rem = pix - v * HW;
+    const int yy = rem / a.W, xx = rem - yy * a.W;
+    double ps[3], d[3], x[3];
+    sphere_point_f64(a.cams.c[v], xx, yy, (double)a.grid.bg_radius, ps, d);
+    contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+    for (int lev = 0; lev < a.grid.L; ++lev) {
+      const int res = a.grid.res[lev];
+      int ci[3];
+      float wv[3];
+      grid_cell(x, res, ci, wv);
+      const uint32_t side = (uint32_t)res + 1u;
+      const bool drn = (a.grid.dense_rad >> lev) & 1u;
+      float2 df = make_float2(0.f, 0.f);
+      if (valid) df = *reinterpret_cast<const float2*>(a.dfeat_bg + (size_t)pix * 2 * a.grid.L + 2 * lev);
+      const bool use_map = res <= MAP_MAX_RES;
+      const bool seg = res <= MAP_SEG_RES;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+        const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
+        const uint32_t row = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
+                                        a.grid.mask_rad);
+        const float v0 = wc * df.x, v1 = wc * df.y;
+        if (seg) {
+          uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f);
+#pragma unroll 1
+          for (int it = 0; it < 4 && pending; ++it) {
+            const int lead = __ffsll((long long)pending) - 1;
+            const uint32_t keyL = __shfl(row, lead, 64);
+            const bool mine = ((pending >> lane) & 1ull) && row == keyL;
+            float s0 = mine ? v0 : 0.f, s1 = mine ? v1 : 0.f;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+              s0 += __shfl_xor(s0, off, 64);
+              s1 += __shfl_xor(s1, off, 64);
+            }
+            if (lane == lead) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, keyL, s0, s1, use_map);
+            pending &= ~__ballot(mine);
+          }
+          if ((pending >> lane) & 1ull) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, false);
+        } else {
+          map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, false);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < MAP_SLOTS; k += 256) {
+    const uint32_t key = map_key[k];
+    if (key != MAP_EMPTY) {
+      const float2 vv = map_val[k];
+      if (vv.x != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2, vv.x);
+      if (vv.y != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2 + 1, vv.y);
+    }
+  }
+}
+
 __global__ void k_dw_reduce(const float* __restrict__ part, int nparts, int nw, float* __restrict__ gg,
                             float* __restrict__ gc, int n_geo) {
   const int i = blockIdx.x * 256 + threadIdx.x;
@@ -752,6 +774,16 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
     k_field_bwd<Sh, true><<<L.blocks_r, BWD_NT, 0, st>>>(b);
     parts += L.blocks_r;
+    if (a.g_table_rad) {
+      BgGridArgs bg{};
+      bg.grid = a.grid;
+      bg.cams = a.cams;
+      bg.W = a.W;
+      bg.H = a.H;
+      bg.dfeat_bg = a.dfeat_bg;
+      bg.g_table_rad = a.g_table_rad;
+      k_bg_grid_bwd<<<BG_GRID_BLOCKS, 256, 0, st>>>(bg);
+    }
   }
   k_dw_reduce<<<nblk(a.n_w), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col, Sh::N_GEO);
 }

@@ -296,7 +296,7 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
     fs = A.hyrf_fwd_state(C.pointer(qout), C.pointer(spc), st.vals.data_ptr(), st.ranges.data_ptr(),
                           st.T.data_ptr(), st.last.data_ptr(), st.bg.data_ptr())
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
-    nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1))
+    nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1), cams[0].width, cams[0].height)
     w = ws.get("backward", nb)
     A.check("hyrf_render_backward",
             lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL), C.byref(cg),
