@@ -194,6 +194,13 @@ def main():
 
     # precision variant: float16 tables, bfloat16 decoder operands
     dv = ds.with_precision(P.F16, P.BF16)
+    ds_fp32 = ds
+    ds = dv
+    ms_train_v, ev_tv, _ = timed(train_step, args.steps)
+    st_train_v = stages(ev_tv, fwd_keys + (("backward", "bwd0", "bwd1"),))
+    ds = ds_fp32
+    print(f"[bench] train step (f16 tables, bf16 MLP) {ms_train_v:.3f} ms; stages {st_train_v}",
+          file=sys.stderr, flush=True)
     ms_render_v, ev_v, _ = timed(lambda ev: P.render(dv, cams, P.RENDER, ws=ws, events=ev), args.steps)
     st_render_v = stages(ev_v, fwd_keys)
     print(f"[bench] render (f16 tables, bf16 MLP) {ms_render_v:.3f} ms/frame; stages {st_render_v}",
@@ -226,7 +233,8 @@ def main():
            "stage_ms_render": {k: round(v, 4) for k, v in st_render.items()},
            "variant_f16_bf16": {"render_ms": round(ms_render_v, 4), "render_fps": round(1000.0 / ms_render_v, 2),
                                 "stage_ms_render": {k: round(v, 4) for k, v in st_render_v.items()},
-                                "train_step_ms": None},
+                                "train_step_ms": round(ms_train_v, 4),
+                                "stage_ms_train": {k: round(v, 4) for k, v in st_train_v.items()}},
            "tile_entries": st.n_entries,
            "roofline": roof}
     if not args.no_cpu_baseline:

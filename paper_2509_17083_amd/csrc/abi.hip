@@ -382,8 +382,6 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   if ((s = check_fields(fields)) != HYRF_OK) return s;
   if ((s = check_gauss(g)) != HYRF_OK) return s;
   if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
-  if (fields->table_dtype != HYRF_F32 || fields->mlp_dtype != HYRF_F32)
-    return fail(HYRF_ERR_UNSUPPORTED, "the backward of float16-table / bfloat16-decoder fields is not built");
   REQ(saved && saved->query && saved->splats, "saved forward state is incomplete");
   const hyrf_query_out* q = saved->query;
   const hyrf_splats* sp = saved->splats;
@@ -439,8 +437,8 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   FieldBwdArgs& F = L.field;
   F.grid = make_grid(fields);
   F.cams = cc;
-  F.table_geo = (const float*)fields->table_geo;
-  F.table_rad = (const float*)fields->table_rad;
+  F.table_geo = fields->table_geo;
+  F.table_rad = fields->table_rad;
   F.n = g->n;
   F.count = q->vis_count;
   F.vis_idx = q->vis_idx;
@@ -473,6 +471,8 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   L.blocks_g = (int)(rg < 1 ? 1 : (rg > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rg));
   L.blocks_r = (int)(rr < 1 ? 1 : (rr > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rr));
   L.with_bg = true;
+  L.f16 = fields->table_dtype == HYRF_F16;
+  L.bf = fields->mlp_dtype == HYRF_BF16;
   L.g_mlp_geo = grads->mlp_geo;
   L.g_mlp_col = grads->mlp_col;
   launch_backward(fields->levels, fields->hidden, fields->n_hidden, L, st);

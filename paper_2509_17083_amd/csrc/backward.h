@@ -45,12 +45,12 @@ struct ProjBwdArgs {
 struct FieldBwdArgs {
   GridP grid;
   Cams cams;
-  const float* table_geo;
-  const float* table_rad;
-  const float* wf_geo;
-  const float* wf_col;
-  const float* wb_geo;
-  const float* wb_col;
+  const void* table_geo;       // float32 or float16 pairs
+  const void* table_rad;
+  const void* wf_geo;          // permuted decoder weights (float32 or bfloat16)
+  const void* wf_col;
+  const void* wb_geo;
+  const void* wb_col;
   int n;
   const int32_t* count;
   const int32_t* vis_idx;
@@ -80,8 +80,8 @@ struct GridBwdArgs {
   const int32_t* count;
   const int32_t* vis_idx;
   const float* pos;
-  const float* table_geo;
-  const float* table_rad;
+  const void* table_geo;
+  const void* table_rad;
   const float* dfeat_geo;
   const float* dfeat_rad;
   float* g_pos;
@@ -111,6 +111,7 @@ struct BwdLaunch {
   float* wb_col;
   int blocks_g, blocks_r;
   bool with_bg;
+  bool f16, bf;          // float16 tables / bfloat16 decoder operands
   float* g_mlp_geo;
   float* g_mlp_col;
 };

@@ -20,6 +20,8 @@
 #include "kernels.h"
 #include "query.h"
 
+#include <type_traits>
+
 namespace hyrf {
 
 constexpr int GS = 9;   // per-splat gradient record: u, v, conic a, b, c, opacity, r, g, b
@@ -270,15 +272,41 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
 }
 
 // ---------------------------------------------------------------- fields
-template <class Sh>
-__global__ void k_prep_weights(const float* wg, const float* wc, float* fg, float* fc, float* bg, float* bc) {
+template <class Sh, bool BF>
+__global__ void k_prep_weights(const float* wg, const float* wc, void* fg, void* fc, void* bg, void* bc) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  permute_mlp_fwd<Sh>(fg, wg, false, tid, stride);
-  permute_mlp_fwd<Sh>(fc, wc, true, tid, stride);
-  permute_mlp_bwd<Sh>(bg, wg, false, tid, stride);
-  permute_mlp_bwd<Sh>(bc, wc, true, tid, stride);
+  if constexpr (BF) {
+    permute_mlp_fwd_bf16<Sh>((__bf16*)fg, wg, false, tid, stride);
+    permute_mlp_fwd_bf16<Sh>((__bf16*)fc, wc, true, tid, stride);
+    permute_mlp_bwd_bf16<Sh>((__bf16*)bg, wg, false, tid, stride);
+    permute_mlp_bwd_bf16<Sh>((__bf16*)bc, wc, true, tid, stride);
+  } else {
+    permute_mlp_fwd<Sh>((float*)fg, wg, false, tid, stride);
+    permute_mlp_fwd<Sh>((float*)fc, wc, true, tid, stride);
+    permute_mlp_bwd<Sh>((float*)bg, wg, false, tid, stride);
+    permute_mlp_bwd<Sh>((float*)bc, wc, true, tid, stride);
+  }
 }
+
+// Decoder recompute / adjoint in the chosen operand precision.
+template <class Sh, bool BF>
+struct Dec {
+  using T = typename std::conditional<BF, __bf16, float>::type;
+  static constexpr int SG = BF ? Sh::S_GEO1_8 : Sh::S_GEO1;
+  static constexpr int SC = BF ? Sh::S_COL1_8 : Sh::S_COL1;
+  template <int S1>
+  static __device__ void fwd(const void* W, const float (&x)[S1], float (&h)[Sh::NH][Sh::S_HID], v4f& o, int lane) {
+    if constexpr (BF) mlp_forward_keep_bf16<Sh, S1>((const __bf16*)W, x, h, o, lane);
+    else mlp_forward_keep<Sh, S1>((const float*)W, x, h, o, lane);
+  }
+  template <bool COL, int S1, int ACC>
+  static __device__ void bwd(const void* W, const float (&x)[S1], const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                             float (&dx)[S1], float* Xs, float* Ys, v4f (&acc)[ACC], int w, int lane) {
+    if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+    else mlp_backward<Sh, COL, S1, ACC>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+  }
+};
 
 // Write the dW tiles of one layer (tile ids ID0 ..) owned by this wave.
 template <int ID0, int TO, int TI, int ACC>
@@ -380,9 +408,10 @@ __device__ __forceinline__ void map_or_global_add(uint32_t* mk, float2* mv, floa
   if (v1 != 0.f) atomicAdd(tr + 1, v1);
 }
 
-template <class Sh, bool RAY>
+template <class Sh, bool RAY, class TT, bool BF>
 __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   using B = BwdShape<Sh>;
+  using D = Dec<Sh, BF>;
   constexpr int ACC = B::ACC;
   __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
   __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
@@ -411,11 +440,11 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
     double x[3];
     float pxf = 0.f, pyf = 0.f, pzf = 0.f;
     int gi = 0, v_r = 0, pix = 0;
-    float dfr[Sh::FPL], dxg[Sh::S_GEO1];
+    float dfr[Sh::FPL], dxg[D::SG];
 #pragma unroll
     for (int s = 0; s < Sh::FPL; ++s) dfr[s] = 0.f;
 #pragma unroll
-    for (int s = 0; s < Sh::S_GEO1; ++s) dxg[s] = 0.f;
+    for (int s = 0; s < D::SG; ++s) dxg[s] = 0.f;
     float dp_dir[3] = {0.f, 0.f, 0.f};
     if constexpr (!RAY) {
       gi = valid ? a.vis_idx[item] : a.vis_idx[0];
@@ -432,12 +461,12 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         fr[2 * k] = vr.x; fr[2 * k + 1] = vr.y;
       }
       // ---- geometry decoder adjoint
-      float x1g[Sh::S_GEO1];
+      float x1g[D::SG];
 #pragma unroll
-      for (int s = 0; s < Sh::S_GEO1; ++s) x1g[s] = s < Sh::FPL ? fg[s] : 0.f;
+      for (int s = 0; s < D::SG; ++s) x1g[s] = s < Sh::FPL ? fg[s] : 0.f;
       float hg[Sh::NH][Sh::S_HID];
       v4f og;
-      mlp_forward_keep<Sh, Sh::S_GEO1>(a.wf_geo, x1g, hg, og, lane);
+      D::template fwd<D::SG>(a.wf_geo, x1g, hg, og, lane);
       v4f dg = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         const float* d = a.dgeo + (size_t)item * 8;
@@ -465,7 +494,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) a.g_rot_e[(size_t)k * a.n + gi] += dr[k];
       }
-      mlp_backward<Sh, false, Sh::S_GEO1, ACC>(a.wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
+      D::template bwd<false, D::SG, ACC>(a.wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
     } else {
       pix = valid ? item : 0;
       v_r = pix / HW;
@@ -474,7 +503,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       double ps[3], d[3];
       sphere_point_f64(a.cams.c[v_r], xx, yy, (double)a.grid.bg_radius, ps, d);
       contract_f64(a.grid, ps[0], ps[1], ps[2], x);
-      gather_lane<Sh::L, false, float>(a.grid, x, g, nullptr, a.table_rad, fg, fr, nullptr, nullptr);
+      gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, (const TT*)a.table_rad, fg, fr, nullptr, nullptr);
       const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
       pxf = (float)(d[0] / dn); pyf = (float)(d[1] / dn); pzf = (float)(d[2] / dn);
       if (!valid) {
@@ -498,13 +527,13 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       }
       float pe[6];
       pe_lane(g, dir[0], dir[1], dir[2], pe);
-      float x1c[Sh::S_COL1];
+      float x1c[D::SC];
 #pragma unroll
-      for (int s = 0; s < Sh::S_COL1; ++s)
+      for (int s = 0; s < D::SC; ++s)
         x1c[s] = !valid ? 0.f : (s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f));
       float hc[Sh::NH][Sh::S_HID];
       v4f oc4;
-      mlp_forward_keep<Sh, Sh::S_COL1>(a.wf_col, x1c, hc, oc4, lane);
+      D::template fwd<D::SC>(a.wf_col, x1c, hc, oc4, lane);
       v4f dc = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         if constexpr (!RAY) {
@@ -520,8 +549,8 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
           }
         }
       }
-      float dxc[Sh::S_COL1];
-      mlp_backward<Sh, true, Sh::S_COL1, ACC>(a.wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+      float dxc[D::SC];
+      D::template bwd<true, D::SC, ACC>(a.wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
       for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
       if constexpr (!RAY) {
@@ -570,7 +599,10 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
 // level per lane.  Scatter-add of w_c * dL/df into both tables (atomics) and
 // dL/dx = sum_c (dL/df . table[c]) dw_c/dx, reduced over the levels, then the
 // contraction Jacobian -> dL/dp.
+template <class TT>
 __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
+  const TT* table_geo = (const TT*)a.table_geo;
+  const TT* table_rad = (const TT*)a.table_rad;
   const int lev = threadIdx.x & 15;
   const int item = blockIdx.x * 16 + (threadIdx.x >> 4);
   const int count = *a.count;
@@ -604,8 +636,8 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
                      cz = (uint32_t)ci[2] + ((c >> 2) & 1);
       rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
       rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-      vg[c] = *reinterpret_cast<const float2*>(a.table_geo + ((size_t)lev * Tg + rg[c]) * 2);
-      vr[c] = *reinterpret_cast<const float2*>(a.table_rad + ((size_t)lev * Tr + rr[c]) * 2);
+      vg[c] = load_entry(table_geo, (size_t)lev * Tg + rg[c]);
+      vr[c] = load_entry(table_rad, (size_t)lev * Tr + rr[c]);
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -743,15 +775,14 @@ __global__ void k_dw_reduce(const float* __restrict__ part, int nparts, int nw, 
 // ---------------------------------------------------------------- launchers
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
-template <class Sh>
+template <class Sh, class TT, bool BF>
 static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
-  using B = BwdShape<Sh>;
   FieldBwdArgs a = L.field;
-  k_prep_weights<Sh><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
+  k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
   a.wf_geo = L.wf_geo; a.wf_col = L.wf_col; a.wb_geo = L.wb_geo; a.wb_col = L.wb_col;
   a.n_w = Sh::N_GEO + Sh::N_COL;
   // Gaussians
-  k_field_bwd<Sh, false><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+  k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
   {
     GridBwdArgs gb{};
     gb.grid = a.grid;
@@ -766,13 +797,13 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.g_pos = a.g_pos;
     gb.g_table_geo = a.g_table_geo;
     gb.g_table_rad = a.g_table_rad;
-    k_grid_bwd<<<(unsigned)((a.n + 15) / 16 > 0 ? (a.n + 15) / 16 : 1), 256, 0, st>>>(gb);
+    k_grid_bwd<TT><<<(unsigned)((a.n + 15) / 16 > 0 ? (a.n + 15) / 16 : 1), 256, 0, st>>>(gb);
   }
   int parts = L.blocks_g;
   if (L.with_bg) {
     FieldBwdArgs b = a;
     b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
-    k_field_bwd<Sh, true><<<L.blocks_r, BWD_NT, 0, st>>>(b);
+    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
     parts += L.blocks_r;
     if (a.g_table_rad) {
       BgGridArgs bg{};
@@ -796,8 +827,16 @@ void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st
   // 2. projection adjoint
   k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
   // 3. decoders + tables (+ background)
-#define X(l, h, k) if (Lv == l && hid == h && nh == k) return launch_bwd_t<Shape<l, h, k>>(L, st);
-  X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
+  if (Lv == 16 && hid == 64 && nh == 2) {
+    using Sh = Shape<16, 64, 2>;
+    if (!L.f16 && !L.bf) return launch_bwd_t<Sh, float, false>(L, st);
+    if (!L.f16 && L.bf) return launch_bwd_t<Sh, float, true>(L, st);
+    if (L.f16 && !L.bf) return launch_bwd_t<Sh, _Float16, false>(L, st);
+    return launch_bwd_t<Sh, _Float16, true>(L, st);
+  }
+  if (L.f16 || L.bf) return;
+#define X(l, h, k) if (Lv == l && hid == h && nh == k) return launch_bwd_t<Shape<l, h, k>, float, false>(L, st);
+  X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
 #undef X
 }
 

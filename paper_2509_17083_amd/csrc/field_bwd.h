@@ -219,4 +219,143 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// Precision variant: bfloat16 operands, float32 accumulation.  The decoder
+// recompute and dX run on v_mfma_f32_16x16x32_bf16 with the weights in the
+// same lane order packed 8 per k-step; dW runs on the float32 MFMA over
+// staged operands already rounded to bfloat16 (their products are exact in
+// float32, so this equals a bfloat16 product with float32 accumulation).
+__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+
+template <class Sh>
+__device__ void permute_mlp_bwd_bf16(__bf16* dst, const float* __restrict__ W, bool colour, int tid, int stride) {
+  const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
+  const int in1 = colour ? Sh::IN_COL : Sh::IN_GEO;
+  const int S1 = colour ? Sh::S_COL1_8 : Sh::S_GEO1_8;
+  const int g1 = Sh::HID * in1;
+  const int g_out = Sh::NH == 2 ? g1 + Sh::HID * Sh::HID : g1;
+  int dst_off = 0;
+  for (int step = 0; step <= Sh::NH; ++step) {
+    const bool out_l = step == 0;
+    const bool first = step == Sh::NH;
+    const int S = out_l ? 8 : Sh::S_HID;
+    const int RT = first ? S1 / 4 : Sh::NT;
+    const int cnt = RT * S * 64;
+    for (int e = tid; e < cnt; e += stride) {
+      const int s8 = e & 7;
+      const int lane = (e >> 3) & 63;
+      const int rest = e >> 9;
+      const int q = rest % (S / 8);
+      const int rt = rest / (S / 8);
+      const int kk = lane >> 4, i = lane & 15;
+      const int s = 8 * q + s8;
+      float val = 0.f;
+      if (out_l) {
+        const int wrow = 4 * kk + s;
+        if (s < 4 && wrow < n_out) val = W[g_out + wrow * Sh::HID + 16 * rt + i];
+      } else {
+        const int wrow = 16 * (s >> 2) + 4 * kk + (s & 3);
+        if (!first) {
+          val = W[g1 + wrow * Sh::HID + 16 * rt + i];
+        } else {
+          const int wcol = first_layer_col<Sh::L>(4 * rt + (i & 3), i >> 2, colour);
+          if (wcol >= 0 && wcol < in1) val = W[wrow * in1 + wcol];
+        }
+      }
+      dst[dst_off + e] = (__bf16)val;
+    }
+    dst_off += cnt;
+  }
+}
+
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward_keep_bf16(const __bf16* __restrict__ Wf, const float (&x1)[S1],
+                                                      float (&h)[Sh::NH][Sh::S_HID], v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer_bf16<Sh::NT, S1>(Wf, x1, acc, lane);
+  const __bf16* W = Wf + Sh::NT * S1 * 64;
+  relu_to_inputs<Sh::NT>(acc, h[0]);
+#pragma unroll
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, h[k - 1], acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(acc, h[k]);
+  }
+  v4f o[1];
+  mfma_layer_bf16<1, Sh::S_HID>(W, h[Sh::NH - 1], o, lane);
+  out = o[0];
+}
+
+template <int N>
+__device__ __forceinline__ void stage_units_bf(float* S, int pt, int g, const float (&v)[N]) {
+#pragma unroll
+  for (int b = 0; b < N / 4; ++b)
+    *reinterpret_cast<float4*>(S + swz(pt, 16 * b + 4 * g)) =
+        make_float4(bf16r(v[4 * b]), bf16r(v[4 * b + 1]), bf16r(v[4 * b + 2]), bf16r(v[4 * b + 3]));
+}
+
+template <class Sh, bool COL, int S1, int ACC>
+__device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb, const float (&x1)[S1],
+                                                  const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                                  float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
+                                                  int w, int lane) {
+  using B = BwdShape<Sh>;
+  static_assert(S1 == (COL ? Sh::S_COL1_8 : Sh::S_GEO1_8), "first-layer width");
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  const int j = lane & 15, g = lane >> 4;
+  const int pt = w * 16 + j;
+  *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) =
+      make_float4(bf16r(dout[0]), bf16r(dout[1]), bf16r(dout[2]), bf16r(dout[3]));
+  stage_units_bf<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
+  __syncthreads();
+  constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
+  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+  __syncthreads();
+  float dh[Sh::S_HID];
+  {
+    const float din[8] = {dout[0], dout[1], dout[2], dout[3], 0.f, 0.f, 0.f, 0.f};
+    v4f acc[Sh::NT];
+    mfma_layer_bf16<Sh::NT, 8>(Wb, din, acc, lane);
+#pragma unroll
+    for (int b = 0; b < Sh::NT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[Sh::NH - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+  }
+  const __bf16* W = Wb + Sh::NT * 8 * 64;
+#pragma unroll
+  for (int k = Sh::NH - 1; k >= 1; --k) {
+    stage_units_bf<Sh::S_HID>(Ys, pt, g, dh);
+    stage_units_bf<Sh::S_HID>(Xs, pt, g, h[k - 1]);
+    __syncthreads();
+    constexpr int TB_H = TB0 + Sh::NT * TI1;
+    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+    __syncthreads();
+    v4f acc[Sh::NT];
+    mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+#pragma unroll
+    for (int b = 0; b < Sh::NT; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+  }
+  stage_units_bf<Sh::S_HID>(Ys, pt, g, dh);
+#pragma unroll
+  for (int s = 0; s < S1; ++s) {
+    const int col = first_layer_col<Sh::L>(s, g, COL);
+    if (col >= 0) Xs[swz(pt, col)] = bf16r(x1[s]);
+  }
+  __syncthreads();
+  dw_tiles<TB0, Sh::NT, TI1, ACC>(Xs, Ys, accW, w, lane);
+  __syncthreads();
+  {
+    v4f acc[S1 / 4];
+    mfma_layer_bf16<S1 / 4, Sh::S_HID>(W, dh, acc, lane);
+#pragma unroll
+    for (int b = 0; b < S1 / 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) dx[4 * b + r] = acc[b][r];
+  }
+}
+
 }  // namespace hyrf
