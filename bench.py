@@ -184,6 +184,10 @@ def main():
 
     fwd_keys = (("query", "query0", "query1"), ("project", "query1", "project1"),
                 ("bin_sort", "bin0", "bin1"), ("composite", "bin1", "composite1"))
+    if args.render_only:
+        ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
+        print(json.dumps({"render_ms": round(ms_render, 4), "stages": stages(ev_r, fwd_keys)}), flush=True)
+        return
     ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
     st_train = stages(ev_t, fwd_keys + (("backward", "bwd0", "bwd1"),))
     print(f"[bench] train step {ms_train:.3f} ms; stages {st_train}; loss {float(loss):.5f}; "
