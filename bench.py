@@ -111,6 +111,9 @@ def main():
                     help="only run a plain 256 MiB device copy (torch) 5 times: the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--render-only", action="store_true", help="time only the render-mode forward")
+    ap.add_argument("--layout", choices=["morton", "seeded"], default="morton",
+                    help="storage order of the Gaussians: Morton order (the library's spatial_order, applied "
+                         "once before timing) or the generator's seeded order")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the render step of this "
@@ -139,6 +142,9 @@ def main():
     scene = hi.make_scene(cfg)
     cams = hi.make_cameras(cfg)
     ds = P.DeviceScene.from_host(scene)
+    if args.layout == "morton":
+        ds = ds.reordered(ds.spatial_order())
+        torch.cuda.synchronize()
     ws = P.Workspace()
     print(f"[bench] {cfg.name}: {cfg.n_gauss} Gaussians, {cfg.width}x{cfg.height}, views {cfg.n_views}",
           file=sys.stderr, flush=True)
@@ -229,6 +235,7 @@ def main():
            "config": {"workload": f"{cfg.name}: {cfg.n_gauss} Gaussians, {cfg.width}x{cfg.height}, "
                                   f"{cfg.n_views} view(s), L={cfg.levels}, T_rad=2^{cfg.log2_T_rad}, "
                                   f"MLP {cfg.n_hidden}x{cfg.hidden}, FP32 fields",
+                      "layout": f"Gaussians stored in {args.layout} order",
                       "step": "train: pre-cull, field query, projection, binning sort, composite, background, "
                               "L1 loss, full backward (gradient buffers zeroed inside the step)"},
            "train_step_ms": round(ms_train, 4), "render_ms": round(ms_render, 4),

@@ -231,6 +231,19 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
 hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n,
                          float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- data layout ------------------------------------------------------------ */
+
+/* Permutation that orders the Gaussians along a Morton (Z-order) curve of
+ * their contracted positions (10 bits per axis, stable for equal codes).
+ * A layout utility run once, outside the render step: storing the Gaussians
+ * as pos[perm[k]] -> slot k puts spatial neighbours into the same wavefront,
+ * which makes the hash-grid gathers and table-gradient atomics of the coarse
+ * levels coherent.  It changes no rendered value except the order of
+ * equal-depth ties (ties are ordered by storage index).  perm: [n] uint32. */
+hyrf_status hyrf_spatial_order(const hyrf_fields* fields, const float* pos, int32_t n, uint32_t* perm,
+                               void* ws, size_t ws_bytes, void* stream);
+size_t hyrf_spatial_order_workspace_bytes(int32_t n);
+
 /* ---- sizing and errors ----------------------------------------------------- */
 size_t hyrf_query_workspace_bytes(int32_t n);
 size_t hyrf_bin_sort_workspace_bytes(int32_t n_views, int32_t n_max, int64_t capacity,

@@ -77,6 +77,8 @@ EXPORTS = {
     "hyrf_backward_workspace_bytes": (C.c_size_t, [C.POINTER(hyrf_fields), C.c_int32, C.c_int32, C.c_int32,
                                                    C.c_int32]),
     "hyrf_l1_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "hyrf_spatial_order": (C.c_int, [C.POINTER(hyrf_fields), P, C.c_int32, P, P, C.c_size_t, P]),
+    "hyrf_spatial_order_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hyrf_last_error": (C.c_char_p, []),
     "hyrf_version": (C.c_char_p, []),
 }

@@ -479,4 +479,22 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   return check_launch();
 }
 
+size_t hyrf_spatial_order_workspace_bytes(int32_t n) { return order_ws_bytes(n); }
+
+hyrf_status hyrf_spatial_order(const hyrf_fields* fields, const float* pos, int32_t n, uint32_t* perm, void* ws,
+                               size_t ws_bytes, void* stream) {
+  REQ(fields, "fields is NULL");
+  REQ(n >= 0, "n must be >= 0");
+  REQ(n == 0 || (pos && perm), "pos / perm is NULL");
+  for (int d = 0; d < 3; ++d) REQ(fields->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
+  REQ(ws && ws_bytes >= order_ws_bytes(n), "spatial_order workspace too small");
+  GridP g{};
+  for (int d = 0; d < 3; ++d) {
+    g.center[d] = fields->aabb_center[d];
+    g.inv_half[d] = fields->aabb_inv_half[d];
+  }
+  launch_order(pos, n, g, perm, ws, (hipStream_t)stream);
+  return check_launch();
+}
+
 }  // extern "C"

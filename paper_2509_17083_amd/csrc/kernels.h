@@ -41,4 +41,8 @@ size_t radix_temp_elems(int64_t n);
 int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
                      uint32_t* temp, hipStream_t s);
 
+// ---- order.hip
+size_t order_ws_bytes(int n);
+void launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st);
+
 }  // namespace hyrf

@@ -84,6 +84,26 @@ class DeviceScene:
                                    table_rad=self.table_rad.to(tt).contiguous(),
                                    table_dtype=table_dtype, mlp_dtype=mlp_dtype)
 
+    def spatial_order(self) -> torch.Tensor:
+        """Morton-order permutation of the Gaussians (computed on the GPU)."""
+        lib = A.load()
+        n = self.n
+        perm = torch.empty(max(n, 1), dtype=torch.int32, device=self.pos.device)
+        w = torch.empty(max(lib.hyrf_spatial_order_workspace_bytes(n), 256), dtype=torch.uint8, device=self.pos.device)
+        f = self.c_fields()
+        A.check("hyrf_spatial_order", lib.hyrf_spatial_order(C.byref(f), _p(self.pos), n, _p(perm), _p(w), w.numel(),
+                                                             _stream()))
+        return perm[:n].long()
+
+    def reordered(self, perm: torch.Tensor) -> "DeviceScene":
+        """The same scene with its Gaussians stored in the order `perm`."""
+        import dataclasses
+
+        def take(t):
+            return None if t is None else t[..., perm].contiguous()
+        return dataclasses.replace(self, pos=take(self.pos), scale_e=take(self.scale_e), rot_e=take(self.rot_e),
+                                   opac_e=take(self.opac_e), col_e=take(self.col_e))
+
     def c_fields(self) -> A.hyrf_fields:
         f = A.hyrf_fields()
         f.levels, f.features = self.levels, 2

@@ -196,3 +196,29 @@ def test_forward_is_deterministic():
     b = P.render(ds, cams, P.TRAIN)
     torch.cuda.synchronize()
     assert torch.equal(a.image, b.image) and torch.equal(a.T, b.T) and torch.equal(a.last, b.last)
+
+
+def test_spatial_order_is_a_permutation_and_render_is_unchanged():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    ds = device_scene(scene)
+    perm = ds.spatial_order()
+    torch.cuda.synchronize()
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(scene.n))
+    # neighbours in the new order are closer in space than in the seeded order
+    pos = scene.pos.T
+    d_new = np.linalg.norm(pos[p[1:]] - pos[p[:-1]], axis=1).mean()
+    d_old = np.linalg.norm(pos[1:] - pos[:-1], axis=1).mean()
+    assert d_new < 0.5 * d_old
+    # the reordered scene renders like the oracle of the reordered scene
+    import copy
+    sc2 = copy.deepcopy(scene)
+    sc2.pos, sc2.scale_e, sc2.rot_e = scene.pos[:, p].copy(), scene.scale_e[:, p].copy(), scene.rot_e[:, p].copy()
+    sc2.opac_e, sc2.col_e = scene.opac_e[p].copy(), scene.col_e[:, p].copy()
+    st = P.render(ds.reordered(perm), cams, P.TRAIN)
+    torch.cuda.synchronize()
+    r = oracle_view(sc2, cams[0], O.TRAIN)
+    res = compare_image(st.image[0].cpu().numpy(), r, O.TRAIN, 64, 64)
+    assert res["ok"], res
