@@ -339,7 +339,7 @@ hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n, float
 }
 
 namespace {
-constexpr int BWD_MAX_BLOCKS = 512;
+constexpr int BWD_MAX_BLOCKS = 256;   // persistent: one 8-wave workgroup per CU
 
 struct BwdWs {
   float *gs, *dgeo, *dcol, *dfeat_geo, *dfeat_rad, *dfeat_bg, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;

@@ -117,9 +117,9 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
         }
       }
       if (__ballot(contrib)) {
-        gu = wave_sum_f32(gu); gv = wave_sum_f32(gv); ga = wave_sum_f32(ga);
-        gb = wave_sum_f32(gb); gc = wave_sum_f32(gc); go = wave_sum_f32(go);
-        gr = wave_sum_f32(gr); gg = wave_sum_f32(gg); gbb = wave_sum_f32(gbb);
+        gu = wave_sum_dpp(gu); gv = wave_sum_dpp(gv); ga = wave_sum_dpp(ga);
+        gb = wave_sum_dpp(gb); gc = wave_sum_dpp(gc); go = wave_sum_dpp(go);
+        gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gbb = wave_sum_dpp(gbb);
         if (lane_id() == 0) {
           const uint32_t id = sid[k];
           if (id < a.n_rec) {
@@ -595,29 +595,62 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   write_dw<Sh, ACC>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
-// Hash-grid adjoint of the surviving Gaussians: 16 lanes per Gaussian, one
-// level per lane.  Scatter-add of w_c * dL/df into both tables (atomics) and
-// dL/dx = sum_c (dL/df . table[c]) dw_c/dx, reduced over the levels, then the
-// contraction Jacobian -> dL/dp.
+// Add (v0, v1) to row `row` of one table level from every lane of the wave,
+// first summing in registers the lanes that hit the same row (up to 4 distinct
+// rows per call, the rest add alone).  Spatially ordered points share the
+// coarse cells, so one atomic then serves many lanes.  Every lane of the wave
+// must call it (ballots); lanes with nothing to add pass zeros.
+__device__ __forceinline__ void wave_row_add(float* tab, uint32_t row, float v0, float v1, bool reduce) {
+  const int lane = lane_id();
+  if (!reduce) {
+    if (v0 != 0.f) atomicAdd(tab + (size_t)row * 2, v0);
+    if (v1 != 0.f) atomicAdd(tab + (size_t)row * 2 + 1, v1);
+    return;
+  }
+  uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f);
+#pragma unroll 1
+  for (int it = 0; it < 4 && pending; ++it) {
+    const int lead = __ffsll((long long)pending) - 1;
+    const uint32_t key = __shfl(row, lead, 64);
+    const bool mine = ((pending >> lane) & 1ull) && row == key;
+    const float s0 = wave_sum_dpp(mine ? v0 : 0.f);
+    const float s1 = wave_sum_dpp(mine ? v1 : 0.f);
+    if (lane == lead) {
+      if (s0 != 0.f) atomicAdd(tab + (size_t)key * 2, s0);
+      if (s1 != 0.f) atomicAdd(tab + (size_t)key * 2 + 1, s1);
+    }
+    pending &= ~__ballot(mine);
+  }
+  if ((pending >> lane) & 1ull) {
+    if (v0 != 0.f) atomicAdd(tab + (size_t)row * 2, v0);
+    if (v1 != 0.f) atomicAdd(tab + (size_t)row * 2 + 1, v1);
+  }
+}
+
+constexpr int GRID_SEG_RES = 182;   // Gaussians: levels up to this resolution pre-reduce equal rows
+
+// Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
+// levels per lane: scatter-add of w_c * dL/df into both tables and
+// dL/dx = sum_c (dL/df . table[c]) dw_c/dx, then the contraction Jacobian ->
+// dL/dp.
 template <class TT>
 __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   const TT* table_geo = (const TT*)a.table_geo;
   const TT* table_rad = (const TT*)a.table_rad;
-  const int lev = threadIdx.x & 15;
-  const int item = blockIdx.x * 16 + (threadIdx.x >> 4);
+  const int item = blockIdx.x * 256 + threadIdx.x;
   const int count = *a.count;
-  const bool valid = item < count && lev < a.grid.L;
-  float dxv[3] = {0.f, 0.f, 0.f};
-  int gi = 0;
+  if (blockIdx.x * 256 >= count) return;          // whole workgroup idle (uniform)
+  const bool valid = item < count;
+  const int gi = valid ? a.vis_idx[item] : 0;
   float pxf = 0.f, pyf = 0.f, pzf = 0.f;
-  if (item < count) {
-    gi = a.vis_idx[item];
+  if (valid) {
     pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
   }
-  if (valid) {
-    const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
-    double x[3];
-    contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
+  const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
+  double x[3];
+  contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
+  float dxv[3] = {0.f, 0.f, 0.f};
+  for (int lev = 0; lev < a.grid.L; ++lev) {
     const int res = a.grid.res[lev];
     int ci[3];
     float wv[3];
@@ -625,9 +658,13 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
     const uint32_t side = (uint32_t)res + 1u;
     const bool dgn = (a.grid.dense_geo >> lev) & 1u;
     const bool drn = (a.grid.dense_rad >> lev) & 1u;
-    const float2 dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
-    const float2 dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
+    float2 dg = make_float2(0.f, 0.f), dr = dg;
+    if (valid) {
+      dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
+      dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
+    }
     const float fres = (float)res;
+    const bool reduce = res <= GRID_SEG_RES;
     uint32_t rg[8], rr[8];
     float2 vg[8], vr[8];
 #pragma unroll
@@ -636,8 +673,8 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
                      cz = (uint32_t)ci[2] + ((c >> 2) & 1);
       rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
       rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-      vg[c] = load_entry(table_geo, (size_t)lev * Tg + rg[c]);
-      vr[c] = load_entry(table_rad, (size_t)lev * Tr + rr[c]);
+      vg[c] = valid ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
+      vr[c] = valid ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
@@ -646,27 +683,15 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       const float wy = by ? wv[1] : 1.f - wv[1];
       const float wz = bz ? wv[2] : 1.f - wv[2];
       const float wc = (wx * wy) * wz;
-      if (a.g_table_geo) {
-        float* p = a.g_table_geo + ((size_t)lev * Tg + rg[c]) * 2;
-        if (dg.x != 0.f) atomicAdd(p, wc * dg.x);
-        if (dg.y != 0.f) atomicAdd(p + 1, wc * dg.y);
-      }
-      if (a.g_table_rad) {
-        float* p = a.g_table_rad + ((size_t)lev * Tr + rr[c]) * 2;
-        if (dr.x != 0.f) atomicAdd(p, wc * dr.x);
-        if (dr.y != 0.f) atomicAdd(p + 1, wc * dr.y);
-      }
+      if (a.g_table_geo) wave_row_add(a.g_table_geo + (size_t)lev * Tg * 2, rg[c], wc * dg.x, wc * dg.y, reduce);
+      if (a.g_table_rad) wave_row_add(a.g_table_rad + (size_t)lev * Tr * 2, rr[c], wc * dr.x, wc * dr.y, reduce);
       const float val = (dg.x * vg[c].x + dg.y * vg[c].y) + (dr.x * vr[c].x + dr.y * vr[c].y);
       dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);
       dxv[1] += val * fres * (by ? 1.f : -1.f) * (wx * wz);
       dxv[2] += val * fres * (bz ? 1.f : -1.f) * (wx * wy);
     }
   }
-#pragma unroll
-  for (int k = 0; k < 3; ++k)
-#pragma unroll
-    for (int off = 1; off < 16; off <<= 1) dxv[k] += __shfl_xor(dxv[k], off, 64);
-  if (item < count && lev == 0 && a.g_pos) {
+  if (valid && a.g_pos) {
     float dp[3];
     contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
 #pragma unroll
@@ -759,16 +784,25 @@ __global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
   }
 }
 
-__global__ void k_dw_reduce(const float* __restrict__ part, int nparts, int nw, float* __restrict__ gg,
-                            float* __restrict__ gc, int n_geo) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= nw) return;
+// dW partials [nparts][nw] -> grads: 64 weights x 4 part-slices per
+// workgroup, slices combined in a fixed order (deterministic).
+__global__ __launch_bounds__(256) void k_dw_reduce(const float* __restrict__ part, int nparts, int nw,
+                                                   float* __restrict__ gg, float* __restrict__ gc, int n_geo) {
+  __shared__ float sh[4][64];
+  const int wi = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int sl = threadIdx.x >> 6;
   float s = 0.f;
-  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * nw + i];
-  if (i < n_geo) {
-    if (gg) gg[i] += s;
-  } else if (gc) {
-    gc[i - n_geo] += s;
+  if (wi < nw)
+    for (int b = sl; b < nparts; b += 4) s += part[(size_t)b * nw + wi];
+  sh[sl][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (sl == 0 && wi < nw) {
+    const float t = (sh[0][threadIdx.x] + sh[1][threadIdx.x]) + (sh[2][threadIdx.x] + sh[3][threadIdx.x]);
+    if (wi < n_geo) {
+      if (gg) gg[wi] += t;
+    } else if (gc) {
+      gc[wi - n_geo] += t;
+    }
   }
 }
 
@@ -797,7 +831,7 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.g_pos = a.g_pos;
     gb.g_table_geo = a.g_table_geo;
     gb.g_table_rad = a.g_table_rad;
-    k_grid_bwd<TT><<<(unsigned)((a.n + 15) / 16 > 0 ? (a.n + 15) / 16 : 1), 256, 0, st>>>(gb);
+    k_grid_bwd<TT><<<(unsigned)((a.n + 255) / 256 > 0 ? (a.n + 255) / 256 : 1), 256, 0, st>>>(gb);
   }
   int parts = L.blocks_g;
   if (L.with_bg) {
@@ -816,7 +850,7 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
       k_bg_grid_bwd<<<BG_GRID_BLOCKS, 256, 0, st>>>(bg);
     }
   }
-  k_dw_reduce<<<nblk(a.n_w), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col, Sh::N_GEO);
+  k_dw_reduce<<<(unsigned)((a.n_w + 63) / 64), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col, Sh::N_GEO);
 }
 
 void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st) {

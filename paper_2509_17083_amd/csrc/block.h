@@ -26,6 +26,24 @@ __device__ __forceinline__ float wave_sum_f32(float v) {
   return v;
 }
 
+// Sum over the 64 lanes with DPP moves (no LDS crossbar): an inclusive scan
+// inside each 16-lane row (row_shr 1, 2, 4, 8), then row_bcast:15 and
+// row_bcast:31 carry the row totals upward; the total ends in lane 63 and is
+// returned to every lane.
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ float dpp_mov(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xf, BOUND));
+}
+__device__ __forceinline__ float wave_sum_dpp(float v) {
+  v += dpp_mov<0x111, 0xf, true>(v);   // row_shr:1
+  v += dpp_mov<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp_mov<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp_mov<0x118, 0xf, true>(v);   // row_shr:8
+  v += dpp_mov<0x142, 0xa, false>(v);  // row_bcast:15 -> rows 1, 3
+  v += dpp_mov<0x143, 0xc, false>(v);  // row_bcast:31 -> rows 2, 3
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64,
 // at most 1024).  `sh` must hold NT/64 + 1 uint32.  Returns the exclusive
 // prefix of the calling thread; *total receives the workgroup sum.  Contains
