@@ -627,6 +627,33 @@ __device__ __forceinline__ void wave_row_add(float* tab, uint32_t row, float v0,
   }
 }
 
+// Segmented sum over runs of equal `row` in consecutive lanes: every lane
+// ends with the sum of its run's values from the run head up to itself, so
+// the last lane of each run holds the run total (Hillis-Steele scan bounded
+// by the run head).  Returns true in the lanes that hold a run total.
+// Every lane of the wave must call it.
+__device__ __forceinline__ bool wave_run_sum(uint32_t row, float& v0, float& v1) {
+  const int lane = lane_id();
+  const uint32_t prev = __shfl_up(row, 1, 64);
+  const uint32_t next = __shfl_down(row, 1, 64);
+  int head = (lane == 0 || prev != row) ? lane : 0;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const int t = __shfl_up(head, off, 64);
+    if (lane >= off) head = max(head, t);
+  }
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const float t0 = __shfl_up(v0, off, 64);
+    const float t1 = __shfl_up(v1, off, 64);
+    if (lane - off >= head) {
+      v0 += t0;
+      v1 += t1;
+    }
+  }
+  return lane == 63 || next != row;
+}
+
 constexpr int GRID_SEG_RES = 182;   // Gaussians: levels up to this resolution pre-reduce equal rows
 
 // Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
@@ -742,34 +769,16 @@ __global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
       float2 df = make_float2(0.f, 0.f);
       if (valid) df = *reinterpret_cast<const float2*>(a.dfeat_bg + (size_t)pix * 2 * a.grid.L + 2 * lev);
       const bool use_map = res <= MAP_MAX_RES;
-      const bool seg = res <= MAP_SEG_RES;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
         const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
         const uint32_t row = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
                                         a.grid.mask_rad);
-        const float v0 = wc * df.x, v1 = wc * df.y;
-        if (seg) {
-          uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f);
-#pragma unroll 1
-          for (int it = 0; it < 4 && pending; ++it) {
-            const int lead = __ffsll((long long)pending) - 1;
-            const uint32_t keyL = __shfl(row, lead, 64);
-            const bool mine = ((pending >> lane) & 1ull) && row == keyL;
-            float s0 = mine ? v0 : 0.f, s1 = mine ? v1 : 0.f;
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-              s0 += __shfl_xor(s0, off, 64);
-              s1 += __shfl_xor(s1, off, 64);
-            }
-            if (lane == lead) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, keyL, s0, s1, use_map);
-            pending &= ~__ballot(mine);
-          }
-          if ((pending >> lane) & 1ull) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, false);
-        } else {
-          map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, false);
-        }
+        float v0 = wc * df.x, v1 = wc * df.y;
+        // consecutive pixels of a row share the corner rows of a cell:
+        // one add per run of equal rows (no colliding lanes in an atomic)
+        if (wave_run_sum(row, v0, v1)) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, use_map);
       }
     }
   }
