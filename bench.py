@@ -169,7 +169,7 @@ def main():
                 t.zero_()
         if ev is not None:
             mark(ev, "bwd0")
-        P.render_backward(ds, cams, st, dL, grads=grads, ws=ws)
+        P.render_backward(ds, cams, st, dL, grads=grads, ws=ws, events=ev)
         if ev is not None:
             mark(ev, "bwd1")
         return st, loss
@@ -195,7 +195,10 @@ def main():
         print(json.dumps({"render_ms": round(ms_render, 4), "stages": stages(ev_r, fwd_keys)}), flush=True)
         return
     ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
-    st_train = stages(ev_t, fwd_keys + (("backward", "bwd0", "bwd1"),))
+    bwd_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage0", "bwd_stage1"),
+                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_stage3"),
+                ("bwd_bg_tables", "bwd_stage3", "bwd_stage4"))
+    st_train = stages(ev_t, fwd_keys + bwd_keys)
     print(f"[bench] train step {ms_train:.3f} ms; stages {st_train}; loss {float(loss):.5f}; "
           f"entries {st.n_entries}", file=sys.stderr, flush=True)
     ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
@@ -207,7 +210,7 @@ def main():
     ds_fp32 = ds
     ds = dv
     ms_train_v, ev_tv, _ = timed(train_step, args.steps)
-    st_train_v = stages(ev_tv, fwd_keys + (("backward", "bwd0", "bwd1"),))
+    st_train_v = stages(ev_tv, fwd_keys + bwd_keys)
     ds = ds_fp32
     print(f"[bench] train step (f16 tables, bf16 MLP) {ms_train_v:.3f} ms; stages {st_train_v}",
           file=sys.stderr, flush=True)
@@ -217,16 +220,29 @@ def main():
           file=sys.stderr, flush=True)
     del dv
 
-    # dominant forward kernel: the field query (gather-bound); algorithmic bytes
-    # per surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
+    # Roofline of the dominant kernel of the train step: the background
+    # points' radiance-table adjoint (k_bg_grid_bwd, alone in backward stage
+    # 3).  Algorithmic bytes per background pixel: its feature gradient read
+    # (2L floats) + for each of L levels x 8 corners one read-modify-write of
+    # the 2-float table row (16 B).
+    n_bg = V * H * W
+    per_px = 2 * cfg.levels * 4 + cfg.levels * 8 * 16
+    bg_ms = st_train["bwd_bg_tables"]
+    ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
+    roof = {"kernel": "k_bg_grid_bwd", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_pixel": per_px, "pixels": n_bg, "kernel_ms": round(bg_ms, 4),
+            "share_of_step": round(bg_ms / ms_train, 3)}
+    # the dominant forward kernel: the field query (gather-bound); bytes per
+    # surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
     # + explicit parameters read (56 B) + aggregated properties written (44 B)
     n_vis = int(st_r.query["vis_count"].item())
     per_g = 2 * cfg.levels * 8 * 2 * 4 + 56 + 44
     q_ms = st_render["query"]
     achieved = n_vis * per_g / (q_ms * 1e-3) / 1e9
-    roof = {"kernel": "k_field_query", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
+    roof_fwd = {"kernel": "k_field_query", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
 
     out = {"metric": METRIC, "value": round(1000.0 / ms_train, 3), "unit": "train steps/s (fwd+L1+bwd)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_train, 4),
@@ -247,7 +263,8 @@ def main():
                                 "train_step_ms": round(ms_train_v, 4),
                                 "stage_ms_train": {k: round(v, 4) for k, v in st_train_v.items()}},
            "tile_entries": st.n_entries,
-           "roofline": roof}
+           "roofline": roof,
+           "roofline_render": roof_fwd}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams[0])

@@ -225,6 +225,22 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
                                  const hyrf_grads* grads, void* ws, size_t ws_bytes,
                                  void* stream);
 
+/* The same adjoint split into its four stages, for callers that interleave
+ * or time them.  Call stage 0, 1, 2, 3 in order on one stream with the same
+ * arguments and workspace (each stage reads what the previous ones left in
+ * the workspace):
+ *   0  blending and projection adjoints (explicit-parameter gradients)
+ *   1  decoder adjoints of the Gaussians and of the background points
+ *      (decoder weight gradients, view-direction part of dL/dp)
+ *   2  hash-table adjoint of the Gaussians (table gradients, dL/dp through
+ *      the interpolation weights and the contraction)
+ *   3  radiance-table adjoint of the background points.
+ * hyrf_render_backward == stages 0..3. */
+hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields, const hyrf_gaussians* g,
+                                       const hyrf_camera* cams, int32_t n_views,
+                                       const hyrf_fwd_state* saved, const float* dL_drgb,
+                                       const hyrf_grads* grads, void* ws, size_t ws_bytes, void* stream);
+
 /* L1 photometric term of the training loss (Sec. 3.4 Eq. 12, lambda = 0):
  * loss[0] = mean |img - target| over n values, grad[i] = sign(img - target)/n
  * (sign(0) = 0).  loss and grad are device pointers; grad may be NULL. */

@@ -70,6 +70,9 @@ EXPORTS = {
     "hyrf_render_backward": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians), C.POINTER(hyrf_camera),
                                        C.c_int32, C.POINTER(hyrf_fwd_state), P, C.POINTER(hyrf_grads), P,
                                        C.c_size_t, P]),
+    "hyrf_render_backward_stage": (C.c_int, [C.c_int32, C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians),
+                                             C.POINTER(hyrf_camera), C.c_int32, C.POINTER(hyrf_fwd_state), P,
+                                             C.POINTER(hyrf_grads), P, C.c_size_t, P]),
     "hyrf_l1_loss": (C.c_int, [P, P, C.c_int64, P, P, P, C.c_size_t, P]),
     "hyrf_query_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hyrf_bin_sort_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]),

@@ -374,10 +374,10 @@ size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views,
   return carve_bwd(nullptr, fields, n_views, n_max, (int64_t)n_views * width * height).bytes;
 }
 
-hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians* g,
+static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hyrf_gaussians* g,
                                  const hyrf_camera* cams, int32_t n_views, const hyrf_fwd_state* saved,
-                                 const float* dL_drgb, const hyrf_grads* grads, void* ws,
-                                 size_t ws_bytes, void* stream) {
+                                 const float* dL_drgb, const hyrf_grads* grads, void* ws, size_t ws_bytes,
+                                 void* stream) {
   hyrf_status s;
   if ((s = check_fields(fields)) != HYRF_OK) return s;
   if ((s = check_gauss(g)) != HYRF_OK) return s;
@@ -400,6 +400,7 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   BwdWs w = carve_bwd(ws, fields, n_views, sp->n_max, (int64_t)n_views * cams[0].width * cams[0].height);
   const int W = cams[0].width, H = cams[0].height;
   BwdLaunch L{};
+  L.stages = stages;
   L.V = n_views;
   L.comp.W = W;
   L.comp.H = H;
@@ -477,6 +478,20 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
   L.g_mlp_col = grads->mlp_col;
   launch_backward(fields->levels, fields->hidden, fields->n_hidden, L, st);
   return check_launch();
+}
+
+hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians* g, const hyrf_camera* cams,
+                                 int32_t n_views, const hyrf_fwd_state* saved, const float* dL_drgb,
+                                 const hyrf_grads* grads, void* ws, size_t ws_bytes, void* stream) {
+  return backward_impl(BWD_STAGE_ALL, fields, g, cams, n_views, saved, dL_drgb, grads, ws, ws_bytes, stream);
+}
+
+hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields, const hyrf_gaussians* g,
+                                       const hyrf_camera* cams, int32_t n_views, const hyrf_fwd_state* saved,
+                                       const float* dL_drgb, const hyrf_grads* grads, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  REQ(stage >= 0 && stage <= 3, "stage = %d outside [0, 3]", stage);
+  return backward_impl(1 << stage, fields, g, cams, n_views, saved, dL_drgb, grads, ws, ws_bytes, stream);
 }
 
 size_t hyrf_spatial_order_workspace_bytes(int32_t n) { return order_ws_bytes(n); }

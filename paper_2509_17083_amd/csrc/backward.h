@@ -97,7 +97,17 @@ struct BgGridArgs {
   float* g_table_rad;
 };
 
+// Stages of the adjoint, in dependency order (each needs the previous ones).
+enum : int {
+  BWD_STAGE_SPLATS = 1,      // blending + projection adjoints -> explicit grads, decoder-output grads
+  BWD_STAGE_DECODERS = 2,    // decoder adjoints (Gaussians, background) -> MLP grads, feature grads
+  BWD_STAGE_TABLES = 4,      // Gaussians' hash-table adjoint -> table grads, position grads
+  BWD_STAGE_BG_TABLES = 8,   // background points' radiance-table adjoint
+  BWD_STAGE_ALL = 15
+};
+
 struct BwdLaunch {
+  int stages;
   int V;
   CompBwdArgs comp;
   int64_t n_gs;

@@ -821,12 +821,22 @@ static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256 > 0 ? (n + 2
 template <class Sh, class TT, bool BF>
 static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
   FieldBwdArgs a = L.field;
-  k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
   a.wf_geo = L.wf_geo; a.wf_col = L.wf_col; a.wb_geo = L.wb_geo; a.wb_col = L.wb_col;
   a.n_w = Sh::N_GEO + Sh::N_COL;
-  // Gaussians
-  k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
-  {
+  if (L.stages & BWD_STAGE_DECODERS) {
+    k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
+    k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+    int parts = L.blocks_g;
+    if (L.with_bg) {
+      FieldBwdArgs b = a;
+      b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
+      k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
+      parts += L.blocks_r;
+    }
+    k_dw_reduce<<<(unsigned)((a.n_w + 63) / 64), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col,
+                                                               Sh::N_GEO);
+  }
+  if (L.stages & BWD_STAGE_TABLES) {
     GridBwdArgs gb{};
     gb.grid = a.grid;
     gb.n = a.n;
@@ -842,34 +852,27 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.g_table_rad = a.g_table_rad;
     k_grid_bwd<TT><<<(unsigned)((a.n + 255) / 256 > 0 ? (a.n + 255) / 256 : 1), 256, 0, st>>>(gb);
   }
-  int parts = L.blocks_g;
-  if (L.with_bg) {
-    FieldBwdArgs b = a;
-    b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
-    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
-    parts += L.blocks_r;
-    if (a.g_table_rad) {
-      BgGridArgs bg{};
-      bg.grid = a.grid;
-      bg.cams = a.cams;
-      bg.W = a.W;
-      bg.H = a.H;
-      bg.dfeat_bg = a.dfeat_bg;
-      bg.g_table_rad = a.g_table_rad;
-      k_bg_grid_bwd<<<BG_GRID_BLOCKS, 256, 0, st>>>(bg);
-    }
+  if ((L.stages & BWD_STAGE_BG_TABLES) && L.with_bg && a.g_table_rad) {
+    BgGridArgs bg{};
+    bg.grid = a.grid;
+    bg.cams = a.cams;
+    bg.W = a.W;
+    bg.H = a.H;
+    bg.dfeat_bg = a.dfeat_bg;
+    bg.g_table_rad = a.g_table_rad;
+    k_bg_grid_bwd<<<BG_GRID_BLOCKS, 256, 0, st>>>(bg);
   }
-  k_dw_reduce<<<(unsigned)((a.n_w + 63) / 64), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col, Sh::N_GEO);
 }
 
 void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st) {
-  // 1. per-splat gradient records
-  k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
-  dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
-  k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
-  // 2. projection adjoint
-  k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
-  // 3. decoders + tables (+ background)
+  if (L.stages & BWD_STAGE_SPLATS) {
+    // per-splat gradient records, then the projection adjoint
+    k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
+    dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
+    k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
+    k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
+  }
+  if (!(L.stages & (BWD_STAGE_DECODERS | BWD_STAGE_TABLES | BWD_STAGE_BG_TABLES))) return;
   if (Lv == 16 && hid == 64 && nh == 2) {
     using Sh = Shape<16, 64, 2>;
     if (!L.f16 && !L.bf) return launch_bwd_t<Sh, float, false>(L, st);

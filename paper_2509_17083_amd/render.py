@@ -293,7 +293,8 @@ def l1_loss(img: torch.Tensor, target: torch.Tensor, grad: bool = True, ws: Opti
 
 
 def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.Tensor,
-                    grads: Optional[Dict[str, torch.Tensor]] = None, ws: Optional[Workspace] = None):
+                    grads: Optional[Dict[str, torch.Tensor]] = None, ws: Optional[Workspace] = None,
+                    events: Optional[dict] = None):
     """Adjoint of a TRAIN-mode `render`: accumulates (+=) gradients of every
     explicit parameter, both tables and both decoders into `grads` (zeroed
     here when not given).  dL_drgb: (V, 3, H, W) float32."""
@@ -318,9 +319,18 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
     nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1), cams[0].width, cams[0].height)
     w = ws.get("backward", nb)
-    A.check("hyrf_render_backward",
-            lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL), C.byref(cg),
-                                     _p(w), w.numel(), _stream()))
+    if events is None:
+        A.check("hyrf_render_backward",
+                lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL), C.byref(cg),
+                                         _p(w), w.numel(), _stream()))
+        return grads
+    # stage by stage, with events between the stages
+    for stage in range(4):
+        _mark(events, f"bwd_stage{stage}")
+        A.check("hyrf_render_backward_stage",
+                lib.hyrf_render_backward_stage(stage, C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL),
+                                               C.byref(cg), _p(w), w.numel(), _stream()))
+    _mark(events, "bwd_stage4")
     return grads
 
 

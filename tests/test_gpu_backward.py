@@ -123,3 +123,18 @@ def test_l1_loss_and_gradient():
     assert abs(float(loss) - float(d.abs().mean())) < 1e-6
     want = torch.sign(d) / d.numel()
     assert torch.equal(g.cpu().double(), want.float().double())
+
+
+def test_staged_backward_equals_one_call():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    ds = device_scene(scene)
+    st = P.render(ds, cams, P.TRAIN)
+    dL = torch.from_numpy(hi.make_target_image((1, 3, 64, 64), seed=8) - 0.5).cuda()
+    g1 = P.render_backward(ds, cams, st, dL)
+    g2 = P.render_backward(ds, cams, st, dL, events={})
+    torch.cuda.synchronize()
+    for k, v in g1.items():
+        if v is not None:
+            assert torch.allclose(g2[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
