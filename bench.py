@@ -31,6 +31,24 @@ def _ms(a, b):
     return a.elapsed_time(b)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter on a
+    plain device copy of known size), or None when the kernel's sources have
+    changed since the counters were taken."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_c1m_fp32.json")) as f:
+            rec = json.load(f)["kernels"][kernel]
+    except (OSError, KeyError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return rec["traffic_bytes"] if h.hexdigest()[:16] == rec["sources_sha256_16"] else None
+
+
 def cpu_baseline(scene, cam):
     """The FP64 oracle (as it stands) on a bounded sample of the same train
     step: forward (field query + aggregation + projection of every 10th
@@ -230,7 +248,8 @@ def main():
     bg_ms = st_train["bwd_bg_tables"]
     ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
     roof = {"kernel": "k_bg_grid_bwd", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_bg_grid_bwd"),
+            "algorithmic_bytes": n_bg * per_px,
             "bytes_per_pixel": per_px, "pixels": n_bg, "kernel_ms": round(bg_ms, 4),
             "share_of_step": round(bg_ms / ms_train, 3)}
     # the dominant forward kernel: the field query (gather-bound); bytes per
@@ -241,7 +260,8 @@ def main():
     q_ms = st_render["query"]
     achieved = n_vis * per_g / (q_ms * 1e-3) / 1e9
     roof_fwd = {"kernel": "k_field_query", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("k_field_query"), "algorithmic_bytes": n_vis * per_g,
                 "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
 
     out = {"metric": METRIC, "value": round(1000.0 / ms_train, 3), "unit": "train steps/s (fwd+L1+bwd)",
