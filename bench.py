@@ -179,9 +179,12 @@ def main():
         e.record()
         ev.setdefault(name, []).append(e)
 
-    def train_step(ev=None):
+    def train_step(ev=None, dssim=False):
         st = P.render(ds, cams, P.TRAIN, ws=ws, events=ev)
-        loss, dL = P.l1_loss(st.image, target, ws=ws)
+        if dssim:
+            loss, dL = P.l1_dssim_loss(st.image, target, lam=0.2, ws=ws)
+        else:
+            loss, dL = P.l1_loss(st.image, target, ws=ws)
         for t in grads.values():
             if t is not None:
                 t.zero_()
@@ -219,6 +222,13 @@ def main():
     st_train = stages(ev_t, fwd_keys + bwd_keys)
     print(f"[bench] train step {ms_train:.3f} ms; stages {st_train}; loss {float(loss):.5f}; "
           f"entries {st.n_entries}", file=sys.stderr, flush=True)
+    # the paper's full training loss: (1 - 0.2) L1 + 0.2 D-SSIM (fused kernel)
+    ms_train_ds, _, _ = timed(lambda ev: train_step(ev, dssim=True), args.steps)
+    img_t = st.image.contiguous()
+    ms_loss_ds, _, _ = timed(lambda ev: P.l1_dssim_loss(img_t, target, lam=0.2, ws=ws), args.steps)
+    ms_loss_l1, _, _ = timed(lambda ev: P.l1_loss(img_t, target, ws=ws), args.steps)
+    print(f"[bench] train step with L1 + D-SSIM {ms_train_ds:.3f} ms; loss kernels: L1+D-SSIM {ms_loss_ds:.4f} ms, "
+          f"L1 {ms_loss_l1:.4f} ms", file=sys.stderr, flush=True)
     ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
     st_render = stages(ev_r, fwd_keys)
     print(f"[bench] render {ms_render:.3f} ms/frame; stages {st_render}", file=sys.stderr, flush=True)
@@ -282,6 +292,9 @@ def main():
                                 "stage_ms_render": {k: round(v, 4) for k, v in st_render_v.items()},
                                 "train_step_ms": round(ms_train_v, 4),
                                 "stage_ms_train": {k: round(v, 4) for k, v in st_train_v.items()}},
+           "train_step_l1_dssim_ms": round(ms_train_ds, 4),
+           "loss_ms": {"l1_dssim_fused": round(ms_loss_ds, 4), "l1": round(ms_loss_l1, 4),
+                       "l1_dssim_hbm_frac": round(12.0 * V * 3 * H * W / (ms_loss_ds * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
            "tile_entries": st.n_entries,
            "roofline": roof,
            "roofline_render": roof_fwd}

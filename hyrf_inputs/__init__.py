@@ -235,3 +235,28 @@ def make_splat_records(n_views: int, n: int, width: int, height: int, seed: int 
     x1 = np.where(empty, x0, x1)
     rect = np.stack([x0, y0, x1, y1], axis=1).astype(np.int32)   # (m, 4)
     return depth.reshape(n_views, n), rect.reshape(n_views, n, 4), tw, th
+
+
+def make_image_pair(shape, seed: int = 2101):
+    """A pair of images in [0, 1] shaped like a rendering and its reference
+    (..., H, W): a smooth random field (a few random plane waves) with pixel
+    noise and a flat patch, and the same field slightly shifted in tone with
+    fresh noise.  Exercises textured, smooth and perfectly flat windows."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    H, W = shape[-2], shape[-1]
+    planes = int(np.prod(shape[:-2])) if len(shape) > 2 else 1
+    yy, xx = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64), indexing="ij")
+    a = np.empty((planes, H, W))
+    b = np.empty((planes, H, W))
+    for p in range(planes):
+        f = np.full((H, W), 0.5)
+        for _ in range(4):
+            kx, ky = rng.uniform(-0.2, 0.2, size=2)
+            f += rng.uniform(0.05, 0.15) * np.sin(kx * xx + ky * yy + rng.uniform(0, 2 * np.pi))
+        a[p] = f + rng.normal(0.0, 0.03, size=(H, W))
+        b[p] = 0.9 * f + 0.05 + rng.normal(0.0, 0.03, size=(H, W))
+        h0, w0 = rng.integers(0, max(1, H // 2)), rng.integers(0, max(1, W // 2))
+        a[p, h0:h0 + H // 4, w0:w0 + W // 4] = 0.25
+        b[p, h0:h0 + H // 4, w0:w0 + W // 4] = 0.3
+    return (np.clip(a, 0, 1).reshape(shape).astype(np.float32),
+            np.clip(b, 0, 1).reshape(shape).astype(np.float32))

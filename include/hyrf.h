@@ -247,6 +247,25 @@ hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields,
 hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n,
                          float* loss, float* grad, void* ws, size_t ws_bytes, void* stream);
 
+/* Training loss of Sec. 3.4 Eq. 12 with both terms:
+ *   loss = (1 - lambda) * mean|img - target| + lambda * (1 - mean SSIM(img, target)),
+ * forward and gradient fused in one pass.  SSIM follows Wang et al. 2004
+ * with the settings 3DGS trains with (the paper adopts its loss): 11 x 11
+ * Gaussian window of standard deviation 1.5, C1 = 0.01^2, C2 = 0.03^2
+ * (dynamic range 1), statistics per plane with the image extended by zeros
+ * outside its frame; the mean runs over every pixel of every plane.
+ * img, target: device [planes][height][width] fp32 (planes = views x 3
+ * colour channels).  loss: device float[3] <- (loss, mean L1, mean SSIM).
+ * grad (device, nullable): [planes][height][width] <- dloss/dimg
+ * (overwritten; sign(0) = 0 in the L1 term).  lambda in [0, 1] (3DGS: 0.2).
+ * Deterministic.  Invalid arguments (NULL, non-positive sizes, lambda out of
+ * range, workspace too small) return HYRF_ERR_INVALID_ARGUMENT before any
+ * launch. */
+hyrf_status hyrf_l1_dssim_loss(const float* img, const float* target, int32_t planes, int32_t height,
+                               int32_t width, float lambda, float* loss, float* grad, void* ws,
+                               size_t ws_bytes, void* stream);
+size_t hyrf_l1_dssim_workspace_bytes(int32_t planes, int32_t height, int32_t width);
+
 /* ---- data layout ------------------------------------------------------------ */
 
 /* Permutation that orders the Gaussians along a Morton (Z-order) curve of

@@ -74,6 +74,8 @@ EXPORTS = {
                                              C.POINTER(hyrf_camera), C.c_int32, C.POINTER(hyrf_fwd_state), P,
                                              C.POINTER(hyrf_grads), P, C.c_size_t, P]),
     "hyrf_l1_loss": (C.c_int, [P, P, C.c_int64, P, P, P, C.c_size_t, P]),
+    "hyrf_l1_dssim_loss": (C.c_int, [P, P, C.c_int32, C.c_int32, C.c_int32, C.c_float, P, P, P, C.c_size_t, P]),
+    "hyrf_l1_dssim_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),
     "hyrf_query_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hyrf_bin_sort_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int64, C.c_int32, C.c_int32]),
     "hyrf_composite_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32, C.c_int32]),

@@ -338,6 +338,24 @@ hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n, float
   return check_launch();
 }
 
+size_t hyrf_l1_dssim_workspace_bytes(int32_t planes, int32_t height, int32_t width) {
+  if (planes <= 0 || height <= 0 || width <= 0) return 0;
+  return l1_dssim_ws_elems(planes, height, width) * sizeof(float);
+}
+
+hyrf_status hyrf_l1_dssim_loss(const float* img, const float* target, int32_t planes, int32_t height,
+                               int32_t width, float lambda, float* loss, float* grad, void* ws,
+                               size_t ws_bytes, void* stream) {
+  REQ(img && target && loss, "img / target / loss is NULL");
+  REQ(planes > 0 && height > 0 && width > 0, "planes / height / width must be positive");
+  REQ(planes <= 65535, "planes = %d exceeds 65535", planes);
+  REQ((int64_t)planes * height * width < (int64_t)1 << 31, "image too large");
+  REQ(lambda >= 0.f && lambda <= 1.f, "lambda = %g outside [0, 1]", (double)lambda);
+  REQ(ws && ws_bytes >= hyrf_l1_dssim_workspace_bytes(planes, height, width), "l1_dssim workspace too small");
+  launch_l1_dssim(img, target, planes, height, width, lambda, loss, grad, (float*)ws, (hipStream_t)stream);
+  return check_launch();
+}
+
 namespace {
 constexpr int BWD_MAX_BLOCKS = 256;   // persistent: one 8-wave workgroup per CU
 

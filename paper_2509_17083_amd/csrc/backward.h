@@ -8,6 +8,11 @@ size_t l1_ws_elems(int64_t n);
 void launch_l1(const float* img, const float* target, int64_t n, float* loss, float* grad, float* ws,
                hipStream_t st);
 
+// ---- ssim.hip
+size_t l1_dssim_ws_elems(int planes, int H, int W);
+void launch_l1_dssim(const float* img, const float* target, int planes, int H, int W, float lambda,
+                     float* loss, float* grad, float* ws, hipStream_t st);
+
 // ---- backward.hip
 struct CompBwdArgs {
   int W, H, tiles_x, tiles_y;

@@ -292,6 +292,24 @@ def l1_loss(img: torch.Tensor, target: torch.Tensor, grad: bool = True, ws: Opti
     return loss, g
 
 
+def l1_dssim_loss(img: torch.Tensor, target: torch.Tensor, lam: float = 0.2, grad: bool = True,
+                  ws: Optional[Workspace] = None):
+    """(1 - lam) L1 + lam (1 - SSIM) of (..., H, W) float32 images and its
+    gradient, fused in one kernel.  Returns (float32[3] = (loss, L1, SSIM),
+    dloss/dimg or None)."""
+    lib = A.load()
+    ws = ws or Workspace()
+    H, W = img.shape[-2], img.shape[-1]
+    planes = img.numel() // (H * W)
+    assert img.is_contiguous() and target.is_contiguous() and target.shape == img.shape
+    loss = torch.empty(3, device="cuda")
+    g = torch.empty_like(img) if grad else None
+    w = ws.get("l1_dssim", lib.hyrf_l1_dssim_workspace_bytes(planes, H, W))
+    A.check("hyrf_l1_dssim_loss", lib.hyrf_l1_dssim_loss(_p(img), _p(target), planes, H, W, float(lam), _p(loss),
+                                                         _p(g), _p(w), w.numel(), _stream()))
+    return loss, g
+
+
 def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.Tensor,
                     grads: Optional[Dict[str, torch.Tensor]] = None, ws: Optional[Workspace] = None,
                     events: Optional[dict] = None):

@@ -126,3 +126,16 @@ def test_workspace_sizes_grow_with_problem():
     b = lib.hyrf_bin_sort_workspace_bytes(1, 1000, 100000, 64, 64)
     assert 0 < a < b
     assert lib.hyrf_composite_workspace_bytes(2, 64, 64) > lib.hyrf_composite_workspace_bytes(1, 64, 64)
+
+
+def test_l1_dssim_rejects_bad_arguments():
+    A, lib = _lib()
+    p = C.c_void_p
+    ws = lib.hyrf_l1_dssim_workspace_bytes(3, 64, 64)
+    assert ws > 0 and lib.hyrf_l1_dssim_workspace_bytes(3, 640, 640) > ws
+    assert lib.hyrf_l1_dssim_workspace_bytes(0, 64, 64) == 0
+    good = [p(0x100), p(0x200), 3, 64, 64, 0.2, p(0x300), p(0x400), p(0x500), ws, None]
+    for i, bad in [(0, None), (2, 0), (3, -1), (5, 1.5), (5, -0.1), (9, ws - 1), (8, None)]:
+        args = list(good)
+        args[i] = bad
+        assert lib.hyrf_l1_dssim_loss(*args) == A.HYRF_ERR_INVALID_ARGUMENT, (i, bad)
