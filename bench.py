@@ -14,6 +14,7 @@ timed step; the JSON also carries the dominant kernel's roofline position
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -248,6 +249,19 @@ def main():
           file=sys.stderr, flush=True)
     del dv
 
+    # compressed model: both tables as 8-bit min-max codes decoded in the gather
+    dq = ds.quantized()
+    ms_render_q, ev_q, st_q = timed(lambda ev: P.render(dq, cams, P.RENDER, ws=ws, events=ev), args.steps)
+    st_render_q = stages(ev_q, fwd_keys)
+    ref_img = P.render(ds, cams, P.RENDER, ws=ws).image.clone()
+    q_img = P.render(dq, cams, P.RENDER, ws=ws).image
+    psnr_q = float(-10.0 * torch.log10(torch.mean((q_img - ref_img) ** 2)))
+    dqb = dataclasses.replace(dq, mlp_dtype=P.BF16)
+    ms_render_qb, _, _ = timed(lambda ev: P.render(dqb, cams, P.RENDER, ws=ws, events=ev), args.steps)
+    print(f"[bench] render (u8 tables) {ms_render_q:.3f} ms/frame; stages {st_render_q}; PSNR vs FP32 render "
+          f"{psnr_q:.2f} dB; with bf16 decoders {ms_render_qb:.3f} ms", file=sys.stderr, flush=True)
+    del dq, dqb
+
     # Roofline of the dominant kernel of the train step: the background
     # points' radiance-table adjoint (k_bg_grid_bwd, alone in backward stage
     # 3).  Algorithmic bytes per background pixel: its feature gradient read
@@ -292,6 +306,10 @@ def main():
                                 "stage_ms_render": {k: round(v, 4) for k, v in st_render_v.items()},
                                 "train_step_ms": round(ms_train_v, 4),
                                 "stage_ms_train": {k: round(v, 4) for k, v in st_train_v.items()}},
+           "compressed_u8_tables": {"render_ms": round(ms_render_q, 4), "render_fps": round(1000.0 / ms_render_q, 2),
+                                    "stage_ms_render": {k: round(v, 4) for k, v in st_render_q.items()},
+                                    "render_ms_bf16_decoders": round(ms_render_qb, 4),
+                                    "psnr_vs_fp32_render_db": round(psnr_q, 2)},
            "train_step_l1_dssim_ms": round(ms_train_ds, 4),
            "loss_ms": {"l1_dssim_fused": round(ms_loss_ds, 4), "l1": round(ms_loss_l1, 4),
                        "l1_dssim_hbm_frac": round(12.0 * V * 3 * H * W / (ms_loss_ds * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},

@@ -55,7 +55,7 @@ typedef enum {
   HYRF_ERR_LAUNCH = 4
 } hyrf_status;
 
-typedef enum { HYRF_F32 = 0, HYRF_F16 = 1, HYRF_BF16 = 2 } hyrf_dtype;
+typedef enum { HYRF_F32 = 0, HYRF_F16 = 1, HYRF_BF16 = 2, HYRF_U8 = 3 } hyrf_dtype;
 /* RENDER: the background is added only where the final transmittance
  * exceeds tau_T (Sec. 3.3, last paragraph) and nothing is saved.
  * TRAIN: the background is added at every pixel and the state the backward
@@ -80,7 +80,8 @@ typedef struct {
   int32_t log2_T_rad;    /* radiance table rows per level (10..24)                  */
   float base_res;        /* N_min (>= 2); N_l = floor(N_min * growth^l)             */
   float growth;          /* b (>= 1)                                               */
-  int32_t table_dtype;   /* HYRF_F32 or HYRF_F16                                   */
+  int32_t table_dtype;   /* HYRF_F32, HYRF_F16, or HYRF_U8 (8-bit min-max codes,
+                            render only; see qparams_*)                            */
   const void* table_geo; /* [L][T_geo][2]                                          */
   const void* table_rad; /* [L][T_rad][2]                                          */
   int32_t hidden;        /* MLP width: 16, 32, 48 or 64                            */
@@ -94,6 +95,12 @@ typedef struct {
   float aabb_inv_half[3];
   float bg_radius;       /* background sphere radius r (Sec. 4.1: 100)              */
   float tau_T;           /* render-mode background threshold (Sec. 4.1: 0.2)        */
+  /* HYRF_U8 tables only (else ignored, may be NULL): per level l, the pair
+   * (min_l, step_l) of that level's 8-bit min-max quantisation; an entry
+   * holding code q decodes to min_l + step_l * q (Sec. 4.3, compressed model).
+   * Device, [L][2] float32 each. */
+  const float* qparams_geo;
+  const float* qparams_rad;
 } hyrf_fields;
 
 /* Pinhole camera, world -> camera p_c = R p + t (Sec. 3.3 Eq. 8), OpenCV axes
@@ -265,6 +272,18 @@ hyrf_status hyrf_l1_dssim_loss(const float* img, const float* target, int32_t pl
                                int32_t width, float lambda, float* loss, float* grad, void* ws,
                                size_t ws_bytes, void* stream);
 size_t hyrf_l1_dssim_workspace_bytes(int32_t planes, int32_t height, int32_t width);
+
+/* 8-bit min-max quantisation of one hash table (Sec. 4.3, compressed model),
+ * decoded inside the field gather by every query when table_dtype is HYRF_U8.
+ * Per level l over its T x 2 values: min_l, max_l; step_l = (max_l - min_l) / 255
+ * (float32, correctly rounded); code = rint((x - min_l) / step_l) (float32
+ * subtraction and division, ties to even), clamped to [0, 255]; code 0 when
+ * step_l == 0.  table: device [levels][T][2] float32; codes: device
+ * [levels][T][2] uint8; qparams: device [levels][2] <- (min_l, step_l).
+ * Values must be finite.  Deterministic. */
+hyrf_status hyrf_quantize_table(const float* table, int32_t levels, int32_t log2_T, uint8_t* codes,
+                                float* qparams, void* ws, size_t ws_bytes, void* stream);
+size_t hyrf_quantize_workspace_bytes(int32_t levels, int32_t log2_T);
 
 /* ---- data layout ------------------------------------------------------------ */
 

@@ -5,10 +5,10 @@ C ABI of include/hyrf.h); this package only marshals torch device buffers
 into those calls.
 """
 from . import _abi
-from .render import (BF16, F16, F32, RENDER, TRAIN, DeviceScene, ForwardState, HyRFRender, Workspace, bin_sort,
+from .render import (BF16, F16, F32, U8, RENDER, TRAIN, DeviceScene, ForwardState, HyRFRender, Workspace, bin_sort,
                      c_cameras, composite, l1_dssim_loss, l1_loss, project, query_fields, render, render_backward,
                      render_differentiable)
 
 __all__ = ["DeviceScene", "ForwardState", "Workspace", "render", "query_fields", "project", "bin_sort",
            "composite", "l1_dssim_loss", "l1_loss", "c_cameras", "render_backward", "render_differentiable", "HyRFRender",
-           "RENDER", "TRAIN", "F32", "F16", "BF16"]
+           "RENDER", "TRAIN", "F32", "F16", "BF16", "U8"]

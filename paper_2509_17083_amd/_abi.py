@@ -12,7 +12,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "lib", "libhyrf.so")
 
 HYRF_OK, HYRF_ERR_INVALID_ARGUMENT, HYRF_ERR_UNSUPPORTED, HYRF_ERR_CAPACITY, HYRF_ERR_LAUNCH = range(5)
-HYRF_F32, HYRF_F16, HYRF_BF16 = 0, 1, 2
+HYRF_F32, HYRF_F16, HYRF_BF16, HYRF_U8 = 0, 1, 2, 3
 HYRF_RENDER, HYRF_TRAIN = 0, 1
 TILE = 16
 MAX_VIEWS = 8
@@ -30,7 +30,8 @@ class hyrf_fields(C.Structure):
                 ("table_dtype", C.c_int32), ("table_geo", P), ("table_rad", P),
                 ("hidden", C.c_int32), ("n_hidden", C.c_int32), ("mlp_dtype", C.c_int32),
                 ("mlp_geo", P), ("mlp_col", P), ("aabb_center", C.c_float * 3),
-                ("aabb_inv_half", C.c_float * 3), ("bg_radius", C.c_float), ("tau_T", C.c_float)]
+                ("aabb_inv_half", C.c_float * 3), ("bg_radius", C.c_float), ("tau_T", C.c_float),
+                ("qparams_geo", P), ("qparams_rad", P)]
 
 
 class hyrf_camera(C.Structure):
@@ -82,6 +83,8 @@ EXPORTS = {
     "hyrf_backward_workspace_bytes": (C.c_size_t, [C.POINTER(hyrf_fields), C.c_int32, C.c_int32, C.c_int32,
                                                    C.c_int32]),
     "hyrf_l1_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "hyrf_quantize_table": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P, C.c_size_t, P]),
+    "hyrf_quantize_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "hyrf_spatial_order": (C.c_int, [C.POINTER(hyrf_fields), P, C.c_int32, P, P, C.c_size_t, P]),
     "hyrf_spatial_order_workspace_bytes": (C.c_size_t, [C.c_int32]),
     "hyrf_last_error": (C.c_char_p, []),

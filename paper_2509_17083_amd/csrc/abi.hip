@@ -90,16 +90,18 @@ hyrf_status check_fields(const hyrf_fields* f) {
   REQ(f->n_hidden == 1 || f->n_hidden == 2, "n_hidden must be 1 or 2");
   REQ(f->bg_radius > 0.f, "bg_radius must be positive");
   for (int d = 0; d < 3; ++d) REQ(f->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
-  if (!(f->table_dtype == HYRF_F32 || f->table_dtype == HYRF_F16))
-    return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported (F32 or F16)", f->table_dtype);
+  if (!(f->table_dtype == HYRF_F32 || f->table_dtype == HYRF_F16 || f->table_dtype == HYRF_U8))
+    return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported (F32, F16 or U8)", f->table_dtype);
+  REQ(f->table_dtype != HYRF_U8 || (f->qparams_geo && f->qparams_rad),
+      "8-bit tables need qparams_geo and qparams_rad");
   if (!(f->mlp_dtype == HYRF_F32 || f->mlp_dtype == HYRF_BF16))
     return fail(HYRF_ERR_UNSUPPORTED, "mlp dtype %d not supported (F32 or BF16)", f->mlp_dtype);
   if (!shape_supported(f->levels, f->hidden, f->n_hidden))
     return fail(HYRF_ERR_UNSUPPORTED, "no kernel for levels=%d hidden=%d n_hidden=%d "
                 "(built: 16/64/2, 16/64/1, 8/32/1, 8/64/2)", f->levels, f->hidden, f->n_hidden);
-  if (!precision_supported(f->levels, f->hidden, f->n_hidden, f->table_dtype == HYRF_F16, f->mlp_dtype == HYRF_BF16))
-    return fail(HYRF_ERR_UNSUPPORTED, "float16 tables / bfloat16 decoders are built for levels=16 hidden=64 "
-                "n_hidden=2 only");
+  if (!precision_supported(f->levels, f->hidden, f->n_hidden, f->table_dtype, f->mlp_dtype == HYRF_BF16))
+    return fail(HYRF_ERR_UNSUPPORTED, "float16 tables and bfloat16 decoders are built for levels=16 "
+                "hidden=64 n_hidden=2 only");
   return HYRF_OK;
 }
 
@@ -125,6 +127,8 @@ GridP make_grid(const hyrf_fields* f) {
   }
   g.bg_radius = f->bg_radius;
   g.tau_T = f->tau_T;
+  g.qp_geo = f->table_dtype == HYRF_U8 ? f->qparams_geo : nullptr;
+  g.qp_rad = f->table_dtype == HYRF_U8 ? f->qparams_rad : nullptr;
   return g;
 }
 
@@ -188,7 +192,7 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     a.feat_geo = out->feat_geo;
     a.feat_rad = out->feat_rad;
     a.dbg = out->dbg_index;
-    launch_query(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype == HYRF_F16,
+    launch_query(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype,
                  fields->mlp_dtype == HYRF_BF16, a, g->n, st);
   }
   return check_launch();
@@ -321,7 +325,7 @@ hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const ui
     b.T = out_T;
     b.out_rgb = out_rgb;
     b.bg_save = mode == HYRF_TRAIN ? out_bg : nullptr;
-    launch_bg(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype == HYRF_F16,
+    launch_bg(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype,
               fields->mlp_dtype == HYRF_BF16, b, n_views * W * H, st);
   }
   return check_launch();
@@ -398,6 +402,8 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
                                  void* stream) {
   hyrf_status s;
   if ((s = check_fields(fields)) != HYRF_OK) return s;
+  if (fields->table_dtype == HYRF_U8)
+    return fail(HYRF_ERR_UNSUPPORTED, "8-bit quantised tables are a render-only format (no backward)");
   if ((s = check_gauss(g)) != HYRF_OK) return s;
   if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
   REQ(saved && saved->query && saved->splats, "saved forward state is incomplete");
@@ -513,6 +519,23 @@ hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields,
 }
 
 size_t hyrf_spatial_order_workspace_bytes(int32_t n) { return order_ws_bytes(n); }
+
+size_t hyrf_quantize_workspace_bytes(int32_t levels, int32_t log2_T) {
+  if (levels < 1 || levels > 16 || log2_T < 1 || log2_T > 24) return 0;
+  return quant_ws_elems(levels, log2_T) * sizeof(float);
+}
+
+hyrf_status hyrf_quantize_table(const float* table, int32_t levels, int32_t log2_T, uint8_t* codes,
+                                float* qparams, void* ws, size_t ws_bytes, void* stream) {
+  REQ(table && codes && qparams, "table / codes / qparams is NULL");
+  REQ(levels >= 1 && levels <= 16, "levels = %d outside [1, 16]", levels);
+  REQ(log2_T >= 1 && log2_T <= 24, "log2_T = %d outside [1, 24]", log2_T);
+  REQ(((uintptr_t)table & 15) == 0 && ((uintptr_t)codes & 3) == 0,
+      "table must be 16-byte and codes 4-byte aligned");
+  REQ(ws && ws_bytes >= hyrf_quantize_workspace_bytes(levels, log2_T), "quantize workspace too small");
+  launch_quantize(table, levels, log2_T, codes, qparams, (float*)ws, (hipStream_t)stream);
+  return check_launch();
+}
 
 hyrf_status hyrf_spatial_order(const hyrf_fields* fields, const float* pos, int32_t n, uint32_t* perm, void* ws,
                                size_t ws_bytes, void* stream) {

@@ -17,6 +17,7 @@
 //   input from PE:        k-step L/2 + m of group g = PE value 6g + m
 //   input from a hidden layer: k-step s = 4b + r of group g = unit 16b + 4g + r.
 #pragma once
+#include <type_traits>
 #include "internal.h"
 
 namespace hyrf {
@@ -236,6 +237,14 @@ __device__ __forceinline__ float2 load_entry(const _Float16* t, size_t i) {
   return make_float2((float)v.x, (float)v.y);
 }
 
+// 8-bit min-max codes: the two codes of the entry as floats; the level's
+// affine decode is applied once to the interpolated code (the trilinear
+// weights sum to one).
+__device__ __forceinline__ float2 load_entry(const uint8_t* t, size_t i) {
+  const uchar2 v = *reinterpret_cast<const uchar2*>(t + i * 2);
+  return make_float2((float)v.x, (float)v.y);
+}
+
 // Gather this lane's levels from both tables at contracted position x.
 // fg / fr: lane features (level g + 4k, feature f) at index 2k + f.
 template <int L, bool GEO, class TT>
@@ -282,6 +291,16 @@ __device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], 
       if (GEO) {
         b0 = fmaf(wc[c], vg[c].x, b0);
         b1 = fmaf(wc[c], vg[c].y, b1);
+      }
+    }
+    if constexpr (std::is_same<TT, uint8_t>::value) {
+      const float2 qr = *reinterpret_cast<const float2*>(gp.qp_rad + 2 * lev);
+      a0 = qr.x + qr.y * a0;
+      a1 = qr.x + qr.y * a1;
+      if (GEO) {
+        const float2 qg = *reinterpret_cast<const float2*>(gp.qp_geo + 2 * lev);
+        b0 = qg.x + qg.y * b0;
+        b1 = qg.x + qg.y * b1;
       }
     }
     fr[2 * k] = a0;

@@ -47,6 +47,8 @@ struct GridP {
   int log2_T_geo, log2_T_rad;
   float center[3], inv_half[3];
   float bg_radius, tau_T;
+  const float* qp_geo;   // 8-bit tables: [L][2] (min, step) per level, else NULL
+  const float* qp_rad;
 };
 
 inline CamP to_camp(const hyrf_camera& c) {

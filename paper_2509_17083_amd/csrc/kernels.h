@@ -45,4 +45,9 @@ int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int b
 size_t order_ws_bytes(int n);
 void launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st);
 
+// ---- quant.hip
+size_t quant_ws_elems(int levels, int log2_T);
+void launch_quantize(const float* table, int levels, int log2_T, uint8_t* codes, float* qparams, float* ws,
+                     hipStream_t st);
+
 }  // namespace hyrf

@@ -46,9 +46,9 @@ struct BgArgs {
 
 bool shape_supported(int L, int hid, int nh);
 // f16: tables in float16; bf: decoder operands in bfloat16 (FP32 accumulate).
-bool precision_supported(int L, int hid, int nh, bool f16, bool bf);
-void launch_query(int L, int hid, int nh, bool f16, bool bf, const QueryArgs& a, int n_cap, hipStream_t st);
-void launch_bg(int L, int hid, int nh, bool f16, bool bf, const BgArgs& a, int n_cap, hipStream_t st);
+bool precision_supported(int L, int hid, int nh, int tdt, bool bf);
+void launch_query(int L, int hid, int nh, int tdt, bool bf, const QueryArgs& a, int n_cap, hipStream_t st);
+void launch_bg(int L, int hid, int nh, int tdt, bool bf, const BgArgs& a, int n_cap, hipStream_t st);
 void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
                  uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st);
 

@@ -217,31 +217,39 @@ bool shape_supported(int L, int hid, int nh) {
 
 #define HYRF_SHAPES(X) X(16, 64, 2) X(8, 32, 1) X(16, 64, 1) X(8, 64, 2)
 
+// tdt: table dtype (HYRF_F32, HYRF_F16, HYRF_U8); bf: bfloat16 decoders.
 #define HYRF_DISPATCH(FN, ...)                                                                  \
   do {                                                                                          \
     if (L == 16 && hid == 64 && nh == 2) {                                                      \
       using Sh = Shape<16, 64, 2>;                                                              \
-      if (!f16 && !bf) return FN<Sh, float, false>(__VA_ARGS__);                                \
-      if (!f16 && bf) return FN<Sh, float, true>(__VA_ARGS__);                                  \
-      if (f16 && !bf) return FN<Sh, _Float16, false>(__VA_ARGS__);                              \
-      return FN<Sh, _Float16, true>(__VA_ARGS__);                                               \
+      if (tdt == HYRF_F32) return bf ? FN<Sh, float, true>(__VA_ARGS__) : FN<Sh, float, false>(__VA_ARGS__); \
+      if (tdt == HYRF_F16)                                                                      \
+        return bf ? FN<Sh, _Float16, true>(__VA_ARGS__) : FN<Sh, _Float16, false>(__VA_ARGS__); \
+      if (tdt == HYRF_U8) return bf ? FN<Sh, uint8_t, true>(__VA_ARGS__) : FN<Sh, uint8_t, false>(__VA_ARGS__); \
+      return;                                                                                   \
     }                                                                                           \
-    if (f16 || bf) return;                                                                      \
-    if (L == 8 && hid == 32 && nh == 1) return FN<Shape<8, 32, 1>, float, false>(__VA_ARGS__);  \
-    if (L == 16 && hid == 64 && nh == 1) return FN<Shape<16, 64, 1>, float, false>(__VA_ARGS__); \
-    if (L == 8 && hid == 64 && nh == 2) return FN<Shape<8, 64, 2>, float, false>(__VA_ARGS__);  \
+    if (bf || (tdt != HYRF_F32 && tdt != HYRF_U8)) return;                                      \
+    if (L == 8 && hid == 32 && nh == 1)                                                         \
+      return tdt == HYRF_U8 ? FN<Shape<8, 32, 1>, uint8_t, false>(__VA_ARGS__)                  \
+                            : FN<Shape<8, 32, 1>, float, false>(__VA_ARGS__);                   \
+    if (L == 16 && hid == 64 && nh == 1)                                                        \
+      return tdt == HYRF_U8 ? FN<Shape<16, 64, 1>, uint8_t, false>(__VA_ARGS__)                 \
+                            : FN<Shape<16, 64, 1>, float, false>(__VA_ARGS__);                  \
+    if (L == 8 && hid == 64 && nh == 2)                                                         \
+      return tdt == HYRF_U8 ? FN<Shape<8, 64, 2>, uint8_t, false>(__VA_ARGS__)                  \
+                            : FN<Shape<8, 64, 2>, float, false>(__VA_ARGS__);                   \
   } while (0)
 
-void launch_query(int L, int hid, int nh, bool f16, bool bf, const QueryArgs& a, int n_cap, hipStream_t st) {
+void launch_query(int L, int hid, int nh, int tdt, bool bf, const QueryArgs& a, int n_cap, hipStream_t st) {
   HYRF_DISPATCH(launch_query_t, a, n_cap, st);
 }
 
-void launch_bg(int L, int hid, int nh, bool f16, bool bf, const BgArgs& a, int n_cap, hipStream_t st) {
+void launch_bg(int L, int hid, int nh, int tdt, bool bf, const BgArgs& a, int n_cap, hipStream_t st) {
   HYRF_DISPATCH(launch_bg_t, a, n_cap, st);
 }
 
-bool precision_supported(int L, int hid, int nh, bool f16, bool bf) {
-  if (!f16 && !bf) return shape_supported(L, hid, nh);
+bool precision_supported(int L, int hid, int nh, int tdt, bool bf) {
+  if ((tdt == HYRF_F32 || tdt == HYRF_U8) && !bf) return shape_supported(L, hid, nh);
   return L == 16 && hid == 64 && nh == 2;
 }
 

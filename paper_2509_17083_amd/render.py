@@ -13,7 +13,7 @@ import torch
 
 from . import _abi as A
 
-F32, F16, BF16 = A.HYRF_F32, A.HYRF_F16, A.HYRF_BF16
+F32, F16, BF16, U8 = A.HYRF_F32, A.HYRF_F16, A.HYRF_BF16, A.HYRF_U8
 RENDER, TRAIN = A.HYRF_RENDER, A.HYRF_TRAIN
 
 
@@ -50,6 +50,8 @@ class DeviceScene:
     tau_T: float = 0.2
     table_dtype: int = F32
     mlp_dtype: int = F32
+    qparams_geo: Optional[torch.Tensor] = None   # (L, 2) (min, step) for U8 tables
+    qparams_rad: Optional[torch.Tensor] = None
 
     @property
     def n(self) -> int:
@@ -84,6 +86,26 @@ class DeviceScene:
                                    table_rad=self.table_rad.to(tt).contiguous(),
                                    table_dtype=table_dtype, mlp_dtype=mlp_dtype)
 
+    def quantized(self, mlp_dtype: Optional[int] = None) -> "DeviceScene":
+        """The same scene with both tables stored as 8-bit min-max codes
+        (quantised on the GPU by hyrf_quantize_table); a render-only format."""
+        import dataclasses
+        assert self.table_dtype == F32, "quantise from float32 tables"
+        lib = A.load()
+
+        def q(t, log2_T):
+            codes = torch.empty(t.shape, dtype=torch.uint8, device=t.device)
+            qp = torch.empty(self.levels, 2, dtype=torch.float32, device=t.device)
+            nb = max(lib.hyrf_quantize_workspace_bytes(self.levels, log2_T), 256)
+            w = torch.empty(nb, dtype=torch.uint8, device=t.device)
+            A.check("hyrf_quantize_table", lib.hyrf_quantize_table(_p(t), self.levels, log2_T, _p(codes), _p(qp),
+                                                                   _p(w), w.numel(), _stream()))
+            return codes, qp
+        cg, qg = q(self.table_geo, self.log2_T_geo)
+        cr, qr = q(self.table_rad, self.log2_T_rad)
+        return dataclasses.replace(self, table_geo=cg, table_rad=cr, table_dtype=U8, qparams_geo=qg, qparams_rad=qr,
+                                   mlp_dtype=self.mlp_dtype if mlp_dtype is None else mlp_dtype)
+
     def spatial_order(self) -> torch.Tensor:
         """Morton-order permutation of the Gaussians (computed on the GPU)."""
         lib = A.load()
@@ -116,6 +138,8 @@ class DeviceScene:
         f.aabb_center[:] = list(self.aabb_center)
         f.aabb_inv_half[:] = list(self.aabb_inv_half)
         f.bg_radius, f.tau_T = self.bg_radius, self.tau_T
+        if self.table_dtype == U8:
+            f.qparams_geo, f.qparams_rad = self.qparams_geo.data_ptr(), self.qparams_rad.data_ptr()
         return f
 
     def c_gauss(self) -> A.hyrf_gaussians:
