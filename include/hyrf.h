@@ -157,6 +157,13 @@ typedef struct {
   float* table_rad;      /* [L][T_rad][2] */
   float* mlp_geo;        /* same layout as hyrf_fields.mlp_geo */
   float* mlp_col;        /* same layout as hyrf_fields.mlp_col */
+  /* Densification statistics (Sec. 3.1: Gaussians are densified from
+   * accumulated gradients, as in 3DGS), nullable, [n] each, accumulated (+=)
+   * over calls: for every view in which a Gaussian's footprint touches a tile,
+   * dens_accum += |(W/2 dL/du, H/2 dL/dv)| (the gradient with respect to its
+   * projected centre in normalised device coordinates) and dens_count += 1. */
+  float* dens_accum;
+  float* dens_count;
 } hyrf_grads;
 
 /* Forward state of a TRAIN-mode render that hyrf_render_backward reads. */
@@ -284,6 +291,58 @@ size_t hyrf_l1_dssim_workspace_bytes(int32_t planes, int32_t height, int32_t wid
 hyrf_status hyrf_quantize_table(const float* table, int32_t levels, int32_t log2_T, uint8_t* codes,
                                 float* qparams, void* ws, size_t ws_bytes, void* stream);
 size_t hyrf_quantize_workspace_bytes(int32_t levels, int32_t log2_T);
+
+/* ---- training-loop steps after the backward (Sec. 3.4) ---------------------- */
+
+/* One parameter tensor of hyrf_adam_step.  param, grad, m, v: device [n]
+ * float32 (m and v caller-zeroed before step 1).  param_half (nullable):
+ * device [n] float16 copy written from the updated param (the float16 tables
+ * of the precision variant render from it).  All pointers 16-byte aligned. */
+typedef struct {
+  float* param;
+  float* grad;
+  float* m;
+  float* v;
+  void* param_half;
+  int64_t n;
+  float lr;
+} hyrf_adam_group;
+
+#define HYRF_ADAM_MAX_GROUPS 16
+
+/* Adam (Kingma & Ba 2015, Algorithm 1) over up to HYRF_ADAM_MAX_GROUPS
+ * tensors in one launch -- the explicit Gaussians, both tables and both
+ * decoders train this way (Sec. 3.4; the optimiser of 3DGS): m = b1 m +
+ * (1-b1) g; v = b2 v + (1-b2) g^2; param -= lr (m / (1-b1^t)) /
+ * (sqrt(v / (1-b2^t)) + eps).  step: t >= 1.  zero_grad != 0 clears grad
+ * after reading it (the backward accumulates into zeroed buffers).
+ * groups: HOST array of n_groups descriptors (read during the call).
+ * Invalid arguments return HYRF_ERR_INVALID_ARGUMENT before any launch. */
+hyrf_status hyrf_adam_step(const hyrf_adam_group* groups, int32_t n_groups, int32_t step, float beta1,
+                           float beta2, float eps, int32_t zero_grad, void* stream);
+
+/* Flags of hyrf_densify_masks. */
+#define HYRF_PRUNE 1u   /* opacity below min_opacity                          */
+#define HYRF_CLONE 2u   /* mean NDC gradient >= grad_threshold, small Gaussian */
+#define HYRF_SPLIT 4u   /* mean NDC gradient >= grad_threshold, large Gaussian */
+#define HYRF_JUDGED 8u  /* the Gaussian was in the query's visible list        */
+
+/* Densify / prune decisions of 3DGS applied to HyRF's aggregated Gaussians
+ * (Sec. 3.1 and Sec. 3.4: densify from accumulated gradients, prune
+ * Gaussians with low opacity).  For every Gaussian in the visible list of q
+ * (a query output: vis_count, vis_idx, opacity, scale): mean = dens_accum /
+ * dens_count (0 when the count is 0); CLONE if mean >= grad_threshold and
+ * max(scale) <= dense_extent, SPLIT if mean >= grad_threshold and max(scale) >
+ * dense_extent; PRUNE if opacity < min_opacity; JUDGED always.  Gaussians
+ * outside the list get flags 0.  flags: device [n] uint8 (overwritten).
+ * n_max: the capacity q was written with (its scale stride). */
+hyrf_status hyrf_densify_masks(const hyrf_query_out* q, int32_t n, int32_t n_max, const float* dens_accum,
+                               const float* dens_count, float grad_threshold, float dense_extent,
+                               float min_opacity, uint8_t* flags, void* stream);
+
+/* Opacity reset of Sec. 3.4 (3DGS's periodic reset, applied to the explicit
+ * opacity): opac_e[i] = min(opac_e[i], logit(value)), value in (0, 1). */
+hyrf_status hyrf_reset_opacity(float* opac_e, int32_t n, float value, void* stream);
 
 /* ---- data layout ------------------------------------------------------------ */
 

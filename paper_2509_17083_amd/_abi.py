@@ -51,7 +51,17 @@ class hyrf_splats(C.Structure):
 
 class hyrf_grads(C.Structure):
     _fields_ = [("pos", P), ("scale_e", P), ("rot_e", P), ("opac_e", P), ("col_e", P),
-                ("table_geo", P), ("table_rad", P), ("mlp_geo", P), ("mlp_col", P)]
+                ("table_geo", P), ("table_rad", P), ("mlp_geo", P), ("mlp_col", P),
+                ("dens_accum", P), ("dens_count", P)]
+
+
+class hyrf_adam_group(C.Structure):
+    _fields_ = [("param", P), ("grad", P), ("m", P), ("v", P), ("param_half", P), ("n", C.c_int64),
+                ("lr", C.c_float)]
+
+
+HYRF_PRUNE, HYRF_CLONE, HYRF_SPLIT, HYRF_JUDGED = 1, 2, 4, 8
+ADAM_MAX_GROUPS = 16
 
 
 class hyrf_fwd_state(C.Structure):
@@ -83,6 +93,11 @@ EXPORTS = {
     "hyrf_backward_workspace_bytes": (C.c_size_t, [C.POINTER(hyrf_fields), C.c_int32, C.c_int32, C.c_int32,
                                                    C.c_int32]),
     "hyrf_l1_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "hyrf_adam_step": (C.c_int, [C.POINTER(hyrf_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float,
+                                 C.c_float, C.c_int32, P]),
+    "hyrf_densify_masks": (C.c_int, [C.POINTER(hyrf_query_out), C.c_int32, C.c_int32, P, P, C.c_float, C.c_float,
+                                     C.c_float, P, P]),
+    "hyrf_reset_opacity": (C.c_int, [P, C.c_int32, C.c_float, P]),
     "hyrf_quantize_table": (C.c_int, [P, C.c_int32, C.c_int32, P, P, P, C.c_size_t, P]),
     "hyrf_quantize_workspace_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "hyrf_spatial_order": (C.c_int, [C.POINTER(hyrf_fields), P, C.c_int32, P, P, C.c_size_t, P]),

@@ -417,6 +417,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   REQ(saved->vals && saved->tile_ranges && saved->T_final && saved->last && saved->bg_rgb,
       "saved composite state (vals, tile_ranges, T_final, last, bg_rgb) is incomplete");
   REQ(dL_drgb && grads, "dL_drgb / grads is NULL");
+  REQ(!grads->dens_accum == !grads->dens_count, "dens_accum and dens_count must both be set or both NULL");
   REQ((int64_t)n_views * sp->n_max < ((int64_t)1 << 31), "too many splats");
   const size_t need = hyrf_backward_workspace_bytes(fields, n_views, sp->n_max, cams[0].width, cams[0].height);
   REQ(ws && ws_bytes >= need, "backward workspace too small: %zu < %zu bytes", ws_bytes, need);
@@ -459,6 +460,8 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   L.proj.g_col_e = grads->col_e;
   L.proj.dgeo = w.dgeo;
   L.proj.dcol = w.dcol;
+  L.proj.dens_accum = grads->dens_accum;
+  L.proj.dens_count = grads->dens_accum ? grads->dens_count : nullptr;
   FieldBwdArgs& F = L.field;
   F.grid = make_grid(fields);
   F.cams = cc;
@@ -519,6 +522,47 @@ hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields,
 }
 
 size_t hyrf_spatial_order_workspace_bytes(int32_t n) { return order_ws_bytes(n); }
+
+hyrf_status hyrf_adam_step(const hyrf_adam_group* groups, int32_t n_groups, int32_t step, float beta1,
+                           float beta2, float eps, int32_t zero_grad, void* stream) {
+  REQ(groups, "groups is NULL");
+  REQ(n_groups >= 1 && n_groups <= HYRF_ADAM_MAX_GROUPS, "n_groups = %d outside [1, %d]", n_groups,
+      HYRF_ADAM_MAX_GROUPS);
+  REQ(step >= 1, "step must be >= 1");
+  REQ(beta1 >= 0.f && beta1 < 1.f && beta2 >= 0.f && beta2 < 1.f, "betas must be in [0, 1)");
+  REQ(eps >= 0.f, "eps must be >= 0");
+  for (int k = 0; k < n_groups; ++k) {
+    const hyrf_adam_group& g = groups[k];
+    REQ(g.n >= 0, "group %d: n < 0", k);
+    if (g.n == 0) continue;
+    REQ(g.param && g.grad && g.m && g.v, "group %d: param / grad / m / v is NULL", k);
+    REQ((((uintptr_t)g.param | (uintptr_t)g.grad | (uintptr_t)g.m | (uintptr_t)g.v) & 15) == 0,
+        "group %d: pointers must be 16-byte aligned", k);
+    REQ(((uintptr_t)g.param_half & 1) == 0, "group %d: param_half must be 2-byte aligned", k);
+  }
+  if (adam_launch(groups, n_groups, step, beta1, beta2, eps, zero_grad, (hipStream_t)stream) != 0)
+    return fail(HYRF_ERR_INVALID_ARGUMENT, "too many parameters for one launch");
+  return check_launch();
+}
+
+hyrf_status hyrf_densify_masks(const hyrf_query_out* q, int32_t n, int32_t n_max, const float* dens_accum,
+                               const float* dens_count, float grad_threshold, float dense_extent,
+                               float min_opacity, uint8_t* flags, void* stream) {
+  REQ(q && q->vis_count && q->vis_idx && q->opacity && q->scale, "query output is incomplete");
+  REQ(n >= 1 && n_max >= n, "need 1 <= n <= n_max");
+  REQ(dens_accum && dens_count && flags, "dens_accum / dens_count / flags is NULL");
+  launch_densify_masks(n, n_max, q->vis_count, q->vis_idx, q->opacity, q->scale, dens_accum, dens_count,
+                       grad_threshold, dense_extent, min_opacity, flags, (hipStream_t)stream);
+  return check_launch();
+}
+
+hyrf_status hyrf_reset_opacity(float* opac_e, int32_t n, float value, void* stream) {
+  REQ(opac_e, "opac_e is NULL");
+  REQ(n >= 1, "n must be >= 1");
+  REQ(value > 0.f && value < 1.f, "value must be in (0, 1)");
+  launch_reset_opacity(opac_e, n, value, (hipStream_t)stream);
+  return check_launch();
+}
 
 size_t hyrf_quantize_workspace_bytes(int32_t levels, int32_t log2_T) {
   if (levels < 1 || levels > 16 || log2_T < 1 || log2_T > 24) return 0;

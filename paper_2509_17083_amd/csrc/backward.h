@@ -45,6 +45,8 @@ struct ProjBwdArgs {
   float* g_col_e;
   float* dgeo;           // [n][8] to the decoder adjoint
   float* dcol;           // [n][V][3]
+  float* dens_accum;     // [n] densification statistics, nullable
+  float* dens_count;
 };
 
 struct FieldBwdArgs {

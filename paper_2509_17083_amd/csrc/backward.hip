@@ -162,6 +162,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
   float do_sum = 0.f;
   float dce[3] = {0.f, 0.f, 0.f};
   const float op = a.opacity[s];
+  float dens_g = 0.f, dens_n = 0.f;
   for (int v = 0; v < a.cams.V; ++v) {
     const int4 rc = reinterpret_cast<const int4*>(a.rect)[(size_t)v * a.n_max + s];
     if (!(rc.z > rc.x && rc.w > rc.y)) {   // no tile entries in this view: no gradient
@@ -172,6 +173,12 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     const float* gq = a.gs + ((size_t)v * a.n_max + s) * GS;
     const float du = gq[0], dv = gq[1], dca = gq[2], dcb = gq[3], dcc = gq[4];
     do_sum += gq[5];
+    if (a.dens_accum) {
+      // gradient with respect to the projected centre in NDC: d ndc_x = du * W/2
+      const float nx = du * (0.5f * (float)a.cams.c[v].W), ny = dv * (0.5f * (float)a.cams.c[v].H);
+      dens_g += sqrtf(nx * nx + ny * ny);
+      dens_n += 1.f;
+    }
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const float col = a.rgb[((size_t)v * 3 + c) * n + s];
@@ -254,6 +261,10 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
                            qw * dRq[2][0] + qz * dRq[2][1] - 2.f * qy * dRq[2][2]);
   const float dqz = 2.f * (-2.f * qz * dRq[0][0] - qw * dRq[0][1] + qx * dRq[0][2] + qw * dRq[1][0] - 2.f * qz * dRq[1][1] +
                            qy * dRq[1][2] + qx * dRq[2][0] + qy * dRq[2][1]);
+  if (a.dens_accum) {
+    a.dens_accum[gi] += dens_g;
+    a.dens_count[gi] += dens_n;
+  }
   const float do_pre = do_sum * op * (1.f - op);
   float* dg = a.dgeo + (size_t)s * 8;
   dg[0] = do_pre;

@@ -50,4 +50,13 @@ size_t quant_ws_elems(int levels, int log2_T);
 void launch_quantize(const float* table, int levels, int log2_T, uint8_t* codes, float* qparams, float* ws,
                      hipStream_t st);
 
+// ---- train.hip
+// returns non-zero when the total work does not fit one launch
+int adam_launch(const hyrf_adam_group* groups, int n_groups, int step, float b1, float b2, float eps,
+                int zero_grad, hipStream_t st);
+void launch_densify_masks(int n, int n_max, const int32_t* vis_count, const int32_t* vis_idx,
+                          const float* opacity, const float* scale, const float* accum, const float* count,
+                          float thr, float extent, float min_op, uint8_t* flags, hipStream_t st);
+void launch_reset_opacity(float* opac_e, int n, float value, hipStream_t st);
+
 }  // namespace hyrf

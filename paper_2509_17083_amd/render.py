@@ -354,7 +354,7 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
                      mlp_col=z(scene.mlp_col))
     cg = A.hyrf_grads(*[_p(grads.get(k)) if grads.get(k) is not None else None for k in
                         ("pos", "scale_e", "rot_e", "opac_e", "col_e", "table_geo", "table_rad", "mlp_geo",
-                         "mlp_col")])
+                         "mlp_col", "dens_accum", "dens_count")])
     qout, spc = st.c["qout"], st.c["splats"]
     fs = A.hyrf_fwd_state(C.pointer(qout), C.pointer(spc), st.vals.data_ptr(), st.ranges.data_ptr(),
                           st.T.data_ptr(), st.last.data_ptr(), st.bg.data_ptr())
@@ -374,6 +374,43 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
                                                C.byref(cg), _p(w), w.numel(), _stream()))
     _mark(events, "bwd_stage4")
     return grads
+
+
+def adam_step(groups: Sequence[dict], step: int, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-15,
+              zero_grad: bool = True):
+    """One fused Adam step over up to 16 tensors.  Each group is a dict with
+    float32 CUDA tensors param, grad, m, v (same numel, contiguous), a float
+    lr and optionally a float16 tensor param_half (written from the updated
+    param)."""
+    lib = A.load()
+    arr = (A.hyrf_adam_group * len(groups))()
+    for k, g in enumerate(groups):
+        n = g["param"].numel()
+        for key in ("grad", "m", "v"):
+            assert g[key].numel() == n and g[key].is_contiguous() and g[key].dtype == torch.float32
+        ph = g.get("param_half")
+        arr[k] = A.hyrf_adam_group(g["param"].data_ptr(), g["grad"].data_ptr(), g["m"].data_ptr(),
+                                   g["v"].data_ptr(), None if ph is None else ph.data_ptr(), n, float(g["lr"]))
+    A.check("hyrf_adam_step", lib.hyrf_adam_step(arr, len(groups), int(step), float(beta1), float(beta2),
+                                                 float(eps), int(bool(zero_grad)), _stream()))
+
+
+def densify_masks(st: "ForwardState", n: int, dens_accum: torch.Tensor, dens_count: torch.Tensor,
+                  grad_threshold: float = 2e-4, dense_extent: float = 0.01, min_opacity: float = 0.005):
+    """uint8 flags per Gaussian (HYRF_PRUNE / CLONE / SPLIT / JUDGED) from a
+    forward state's query output and the accumulated statistics."""
+    lib = A.load()
+    flags = torch.empty(n, dtype=torch.uint8, device="cuda")
+    qout = st.c["qout"]
+    A.check("hyrf_densify_masks", lib.hyrf_densify_masks(C.byref(qout), n, n, _p(dens_accum), _p(dens_count),
+                                                         float(grad_threshold), float(dense_extent),
+                                                         float(min_opacity), _p(flags), _stream()))
+    return flags
+
+
+def reset_opacity(opac_e: torch.Tensor, value: float = 0.01):
+    lib = A.load()
+    A.check("hyrf_reset_opacity", lib.hyrf_reset_opacity(_p(opac_e), opac_e.numel(), float(value), _stream()))
 
 
 class HyRFRender(torch.autograd.Function):

@@ -120,3 +120,62 @@ def test_loss_gradient_matches_central_differences():
         xm[idx] -= h
         fd = (float(TO.l1_dssim_loss(xp, y)[0]) - float(TO.l1_dssim_loss(xm, y)[0])) / (2 * h)
         assert abs(fd - float(g[idx])) < 1e-7 * max(1.0, abs(fd)) + 1e-9, (idx, fd, float(g[idx]))
+
+
+# ---------------------------------------------------------------- Adam
+def test_adam_matches_torch_optim_adam():
+    """The library optimiser (torch.optim.Adam, float64) reaches the same
+    parameters after several steps."""
+    rng = np.random.default_rng(11)
+    p0 = rng.normal(size=50)
+    grads = [rng.normal(size=50) * 10 ** rng.uniform(-6, 0, size=50) for _ in range(5)]
+    pt = torch.tensor(p0, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    p, m, v = p0.copy(), np.zeros(50), np.zeros(50)
+    for t, g in enumerate(grads, start=1):
+        pt.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        p, m, v = TO.adam_step(p, g, m, v, t, lr=1e-2, eps=1e-8)
+    assert np.allclose(p, pt.detach().numpy(), rtol=0, atol=1e-14)
+
+
+def test_adam_first_step_is_a_signed_lr_step():
+    """t = 1: m_hat = g and v_hat = g^2, so the update is -lr g / (|g| + eps)."""
+    g = np.array([3.0, -0.5, 1e-3, 0.0])
+    p, m, v = TO.adam_step(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, lr=0.1, eps=1e-15)
+    assert np.allclose(p, -0.1 * g / (np.abs(g) + 1e-15), rtol=1e-13, atol=0)
+    assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_keeps_unit_steps():
+    """With a constant gradient g every bias-corrected step is exactly
+    -lr sign(g) (m_hat = g, v_hat = g^2 for all t)."""
+    p, m, v = np.array([1.0]), np.zeros(1), np.zeros(1)
+    for t in range(1, 8):
+        p, m, v = TO.adam_step(p, np.array([2.0]), m, v, t, lr=0.25, eps=0.0)
+    assert abs(p[0] - (1.0 - 7 * 0.25)) < 1e-12
+
+
+# ---------------------------------------------------------------- densification
+def test_densification_stats_ndc_scaling():
+    acc, cnt = TO.densification_stats([2.0, 1.0, 5.0], [0.0, 1.0, 5.0], 200, 100, [True, True, False])
+    assert np.allclose(acc, [200.0, math.hypot(100.0, 50.0), 0.0]) and list(cnt) == [1.0, 1.0, 0.0]
+
+
+def test_densify_flags_cases():
+    acc = np.array([0.0, 4e-4, 4e-4, 1e-4, 6e-4], np.float32)
+    cnt = np.array([0, 2, 2, 1, 3], np.float32)
+    op = np.array([0.5, 0.5, 0.001, 0.5, 0.004], np.float32)
+    smax = np.array([0.1, 0.005, 0.05, 0.005, 0.5], np.float32)
+    f = TO.densify_flags(acc, cnt, op, smax, threshold=2e-4, dense_extent=0.01, min_opacity=0.005)
+    J, P_, C_, S_ = TO.JUDGED, TO.PRUNE, TO.CLONE, TO.SPLIT
+    # last: float32(6e-4) / 3 rounds to 2.0000001e-4 >= float32(2e-4), so it splits
+    assert list(f) == [J, J | C_, J | S_ | P_, J, J | S_ | P_]
+
+
+def test_reset_opacity_caps_at_logit():
+    x = np.array([-10.0, -4.59511985, 0.0, 3.0], np.float32)
+    r = TO.reset_opacity(x, 0.01)
+    cap = np.float32(math.log(0.01 / 0.99))
+    assert r[0] == np.float32(-10.0) and r[2] == cap and r[3] == cap
+    assert abs(1 / (1 + math.exp(-float(r[3]))) - 0.01) < 1e-8
