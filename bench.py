@@ -249,6 +249,15 @@ def main():
           file=sys.stderr, flush=True)
     del dv
 
+    # single-field (non-decoupled) model: the radiance table feeds both decoders
+    ds_dec = ds
+    ds = ds_dec.as_single_field()
+    ms_train_sf, _, _ = timed(train_step, args.steps)
+    ms_render_sf, _, _ = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
+    ds = ds_dec
+    print(f"[bench] single field: train step {ms_train_sf:.3f} ms, render {ms_render_sf:.3f} ms/frame",
+          file=sys.stderr, flush=True)
+
     # fused Adam over every trained tensor (explicit Gaussians, both tables,
     # both decoders), gradients cleared in the same pass
     names = [k for k in ("pos", "scale_e", "rot_e", "opac_e", "col_e", "table_geo", "table_rad", "mlp_geo",
@@ -331,6 +340,9 @@ def main():
                                     "stage_ms_render": {k: round(v, 4) for k, v in st_render_q.items()},
                                     "render_ms_bf16_decoders": round(ms_render_qb, 4),
                                     "psnr_vs_fp32_render_db": round(psnr_q, 2)},
+           "single_field": {"train_step_ms": round(ms_train_sf, 4), "render_ms": round(ms_render_sf, 4),
+                            "render_fps": round(1000.0 / ms_render_sf, 2),
+                            "table": f"radiance table only, 2^{cfg.log2_T_rad} rows per level"},
            "adam_step": {"ms": round(ms_adam, 4), "parameters": n_params, "bytes_per_parameter": 32,
                          "hbm_frac": round(adam_gbs / HBM_PEAK_GBS, 4)},
            "train_step_l1_dssim_ms": round(ms_train_ds, 4),

@@ -101,6 +101,12 @@ typedef struct {
    * Device, [L][2] float32 each. */
   const float* qparams_geo;
   const float* qparams_rad;
+  /* Non-zero: the single-field (non-decoupled) model the paper compares
+   * with (Sec. 4.4, decoupling ablation): ONE hash grid, the radiance table
+   * (table_rad, log2_T_rad, qparams_rad), feeds both decoders; table_geo,
+   * log2_T_geo and qparams_geo are ignored, and the whole table gradient goes
+   * to hyrf_grads.table_rad (hyrf_grads.table_geo is ignored). */
+  int32_t single_field;
 } hyrf_fields;
 
 /* Pinhole camera, world -> camera p_c = R p + t (Sec. 3.3 Eq. 8), OpenCV axes

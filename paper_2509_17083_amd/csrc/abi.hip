@@ -82,17 +82,18 @@ hyrf_status check_fields(const hyrf_fields* f) {
   REQ(f, "fields is NULL");
   REQ(f->levels == 4 || f->levels == 8 || f->levels == 12 || f->levels == 16, "levels = %d must be 4, 8, 12 or 16", f->levels);
   REQ(f->features == 2, "features per entry must be 2");
-  REQ(f->log2_T_geo >= 10 && f->log2_T_geo <= 24 && f->log2_T_rad >= 10 && f->log2_T_rad <= 24,
+  REQ((f->single_field || (f->log2_T_geo >= 10 && f->log2_T_geo <= 24)) && f->log2_T_rad >= 10 &&
+          f->log2_T_rad <= 24,
       "log2 table sizes must be in [10, 24]");
   REQ(f->base_res >= 2.f && f->growth >= 1.f, "base_res must be >= 2 and growth >= 1");
-  REQ(f->table_geo && f->table_rad && f->mlp_geo && f->mlp_col, "a field array is NULL");
+  REQ((f->single_field || f->table_geo) && f->table_rad && f->mlp_geo && f->mlp_col, "a field array is NULL");
   REQ(f->hidden == 16 || f->hidden == 32 || f->hidden == 48 || f->hidden == 64, "hidden width must be 16, 32, 48 or 64");
   REQ(f->n_hidden == 1 || f->n_hidden == 2, "n_hidden must be 1 or 2");
   REQ(f->bg_radius > 0.f, "bg_radius must be positive");
   for (int d = 0; d < 3; ++d) REQ(f->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
   if (!(f->table_dtype == HYRF_F32 || f->table_dtype == HYRF_F16 || f->table_dtype == HYRF_U8))
     return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported (F32, F16 or U8)", f->table_dtype);
-  REQ(f->table_dtype != HYRF_U8 || (f->qparams_geo && f->qparams_rad),
+  REQ(f->table_dtype != HYRF_U8 || ((f->single_field || f->qparams_geo) && f->qparams_rad),
       "8-bit tables need qparams_geo and qparams_rad");
   if (!(f->mlp_dtype == HYRF_F32 || f->mlp_dtype == HYRF_BF16))
     return fail(HYRF_ERR_UNSUPPORTED, "mlp dtype %d not supported (F32 or BF16)", f->mlp_dtype);
@@ -105,19 +106,24 @@ hyrf_status check_fields(const hyrf_fields* f) {
   return HYRF_OK;
 }
 
+// The geometry field's table: the radiance table in the single-field model.
+const void* geo_table(const hyrf_fields* f) { return f->single_field ? f->table_rad : f->table_geo; }
+
 GridP make_grid(const hyrf_fields* f) {
   GridP g{};
+  const int log2_T_geo = f->single_field ? f->log2_T_rad : f->log2_T_geo;
+  g.single = f->single_field ? 1 : 0;
   g.L = f->levels;
-  g.log2_T_geo = f->log2_T_geo;
+  g.log2_T_geo = log2_T_geo;
   g.log2_T_rad = f->log2_T_rad;
-  g.mask_geo = (1u << f->log2_T_geo) - 1u;
+  g.mask_geo = (1u << log2_T_geo) - 1u;
   g.mask_rad = (1u << f->log2_T_rad) - 1u;
   double s = (double)f->base_res;
   for (int l = 0; l < f->levels; ++l) {
     int res = (int)floor(s);
     g.res[l] = res;
     double side = (double)res + 1.0;
-    if (side * side * side <= (double)(1u << f->log2_T_geo)) g.dense_geo |= 1u << l;
+    if (side * side * side <= (double)(1u << log2_T_geo)) g.dense_geo |= 1u << l;
     if (side * side * side <= (double)(1u << f->log2_T_rad)) g.dense_rad |= 1u << l;
     s = s * (double)f->growth;
   }
@@ -127,7 +133,7 @@ GridP make_grid(const hyrf_fields* f) {
   }
   g.bg_radius = f->bg_radius;
   g.tau_T = f->tau_T;
-  g.qp_geo = f->table_dtype == HYRF_U8 ? f->qparams_geo : nullptr;
+  g.qp_geo = f->table_dtype == HYRF_U8 ? (f->single_field ? f->qparams_rad : f->qparams_geo) : nullptr;
   g.qp_rad = f->table_dtype == HYRF_U8 ? f->qparams_rad : nullptr;
   return g;
 }
@@ -173,7 +179,7 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     QueryArgs a{};
     a.grid = make_grid(fields);
     a.cams = cc;
-    a.table_geo = fields->table_geo;
+    a.table_geo = geo_table(fields);
     a.table_rad = fields->table_rad;
     a.w_geo = fields->mlp_geo;
     a.w_col = fields->mlp_col;
@@ -465,7 +471,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   FieldBwdArgs& F = L.field;
   F.grid = make_grid(fields);
   F.cams = cc;
-  F.table_geo = fields->table_geo;
+  F.table_geo = geo_table(fields);
   F.table_rad = fields->table_rad;
   F.n = g->n;
   F.count = q->vis_count;
@@ -481,7 +487,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.dfeat_bg = w.dfeat_bg;
   F.g_pos = grads->pos;
   F.g_rot_e = grads->rot_e;
-  F.g_table_geo = grads->table_geo;
+  F.g_table_geo = fields->single_field ? nullptr : grads->table_geo;
   F.g_table_rad = grads->table_rad;
   F.dw_part = w.dw_part;
   F.W = W;

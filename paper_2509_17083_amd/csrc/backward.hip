@@ -685,6 +685,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
     pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
   }
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
+  const bool single = a.grid.single != 0;
   double x[3];
   contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
   float dxv[3] = {0.f, 0.f, 0.f};
@@ -701,6 +702,12 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
       dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
     }
+    if (single) {
+      // one field read by both decoders: its feature gradient is the sum
+      dr.x += dg.x;
+      dr.y += dg.y;
+      dg = make_float2(0.f, 0.f);
+    }
     const float fres = (float)res;
     const bool reduce = res <= GRID_SEG_RES;
     uint32_t rg[8], rr[8];
@@ -711,7 +718,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
                      cz = (uint32_t)ci[2] + ((c >> 2) & 1);
       rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
       rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-      vg[c] = valid ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
+      vg[c] = valid && !single ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
       vr[c] = valid ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
     }
 #pragma unroll
@@ -721,7 +728,8 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       const float wy = by ? wv[1] : 1.f - wv[1];
       const float wz = bz ? wv[2] : 1.f - wv[2];
       const float wc = (wx * wy) * wz;
-      if (a.g_table_geo) wave_row_add(a.g_table_geo + (size_t)lev * Tg * 2, rg[c], wc * dg.x, wc * dg.y, reduce);
+      if (a.g_table_geo && !single)
+        wave_row_add(a.g_table_geo + (size_t)lev * Tg * 2, rg[c], wc * dg.x, wc * dg.y, reduce);
       if (a.g_table_rad) wave_row_add(a.g_table_rad + (size_t)lev * Tr * 2, rr[c], wc * dr.x, wc * dr.y, reduce);
       const float val = (dg.x * vg[c].x + dg.y * vg[c].y) + (dr.x * vr[c].x + dr.y * vr[c].y);
       dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);

@@ -49,6 +49,7 @@ struct GridP {
   float bg_radius, tau_T;
   const float* qp_geo;   // 8-bit tables: [L][2] (min, step) per level, else NULL
   const float* qp_rad;
+  int single;            // one field (the radiance table) feeds both decoders
 };
 
 inline CamP to_camp(const hyrf_camera& c) {

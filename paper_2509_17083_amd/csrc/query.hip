@@ -85,7 +85,20 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       dg = a.dbg + (size_t)slot * 2 * Sh::L * 8;
       dr = dg + Sh::L * 8;
     }
-    gather_lane<Sh::L, true, TT>(a.grid, x, g, table_geo, table_rad, fg, fr, dg, dr);
+    if (a.grid.single) {
+      // one field feeds both decoders: gather it once
+      gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, table_rad, fg, fr, nullptr, dr);
+#pragma unroll
+      for (int s = 0; s < Sh::FPL; ++s) fg[s] = fr[s];
+      if (dg) {
+#pragma unroll
+        for (int k = 0; k < Sh::L / 4; ++k)
+#pragma unroll
+          for (int c = 0; c < 8; ++c) dg[(g + 4 * k) * 8 + c] = dr[(g + 4 * k) * 8 + c];
+      }
+    } else {
+      gather_lane<Sh::L, true, TT>(a.grid, x, g, table_geo, table_rad, fg, fr, dg, dr);
+    }
     if (a.feat_geo && valid) {
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {

@@ -52,6 +52,7 @@ class DeviceScene:
     mlp_dtype: int = F32
     qparams_geo: Optional[torch.Tensor] = None   # (L, 2) (min, step) for U8 tables
     qparams_rad: Optional[torch.Tensor] = None
+    single_field: int = 0    # one field (the radiance table) feeds both decoders
 
     @property
     def n(self) -> int:
@@ -106,6 +107,13 @@ class DeviceScene:
         return dataclasses.replace(self, table_geo=cg, table_rad=cr, table_dtype=U8, qparams_geo=qg, qparams_rad=qr,
                                    mlp_dtype=self.mlp_dtype if mlp_dtype is None else mlp_dtype)
 
+    def as_single_field(self) -> "DeviceScene":
+        """The single-field (non-decoupled) model: the radiance table alone
+        feeds both decoders."""
+        import dataclasses
+        return dataclasses.replace(self, table_geo=self.table_rad, log2_T_geo=self.log2_T_rad,
+                                   qparams_geo=self.qparams_rad, single_field=1)
+
     def spatial_order(self) -> torch.Tensor:
         """Morton-order permutation of the Gaussians (computed on the GPU)."""
         lib = A.load()
@@ -140,6 +148,7 @@ class DeviceScene:
         f.bg_radius, f.tau_T = self.bg_radius, self.tau_T
         if self.table_dtype == U8:
             f.qparams_geo, f.qparams_rad = self.qparams_geo.data_ptr(), self.qparams_rad.data_ptr()
+        f.single_field = int(self.single_field)
         return f
 
     def c_gauss(self) -> A.hyrf_gaussians:

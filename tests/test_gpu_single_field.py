@@ -1,0 +1,113 @@
+"""GPU parity of the single-field (non-decoupled) model of the decoupling
+ablation (Sec. 4.4): one hash grid -- the radiance table -- feeds both the
+geometry and the colour decoder.  The oracle is the same step with its
+geometry field bound to the radiance table (one tensor, so its autograd
+gradient is the sum over both uses)."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import hyrf_oracle as O
+from _hyrf_testutil import compare_image, knife_mask, make
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2509_17083_amd as P
+    P._abi.load()
+
+
+def _oracle_single(scene, requires_grad=False):
+    params, fields = O.from_scene(scene, requires_grad=requires_grad)
+    fields.table_geo = fields.table_rad          # one field
+    return params, fields
+
+
+def _device_single(scene):
+    import paper_2509_17083_amd as P
+    return P.DeviceScene.from_host(scene).as_single_field()
+
+
+def test_single_field_indices_and_features():
+    import paper_2509_17083_amd as P
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    ds = _device_single(scene)
+    q, _ = P.query_fields(ds, cams, P.TRAIN, debug_index=True)
+    torch.cuda.synchronize()
+    params, fields = _oracle_single(scene)
+    idx = torch.nonzero(O.precull(params.pos, cams[0]), as_tuple=True)[0]
+    cnt = int(q["vis_count"].item())
+    assert cnt == idx.numel()
+    with torch.no_grad():
+        qo = O.query_gaussians(params, fields, idx, cams[0])
+        _, ir = O.hash_encode(qo["x"], fields.table_rad, fields.resolutions, return_index=True)
+    dbg = q["dbg_index"][:cnt].cpu().numpy().astype(np.int64)
+    assert np.array_equal(dbg[:, 0], ir.numpy()) and np.array_equal(dbg[:, 1], ir.numpy())
+    fg = q["feat_geo"][:cnt].cpu().double()
+    assert float((fg - qo["f_geo"]).abs().max()) < 2e-6
+    assert torch.equal(q["feat_geo"][:cnt], q["feat_rad"][:cnt])
+
+
+@pytest.mark.parametrize("mode", [O.TRAIN, O.RENDER])
+@pytest.mark.parametrize("cfg_name,over", [
+    ("tiny", {}),
+    ("c100k", {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 16}),
+])
+def test_single_field_render_matches_oracle(mode, cfg_name, over):
+    import paper_2509_17083_amd as P
+    _say("case", mode, cfg_name, over)
+    cfg, scene, cams = make(cfg_name, table_init=1.0, **over)
+    scene.scale_e += np.float32(1.0)
+    st = P.render(_device_single(scene), cams, mode)
+    torch.cuda.synchronize()
+    params, fields = _oracle_single(scene)
+    with torch.no_grad():
+        r = O.render_view(params, fields, cams[0], mode, return_stats=True)
+    res = compare_image(st.image[0].cpu().numpy(), r, mode, cams[0].height, cams[0].width)
+    _say("image", res)
+    assert res["ok"], res
+
+
+def test_single_field_backward_matches_oracle():
+    import paper_2509_17083_amd as P
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    cam = cams[0]
+    H, W = cam.height, cam.width
+    w_img = np.random.default_rng(3).normal(size=(3, H, W)).astype(np.float32)
+    params, fields = _oracle_single(scene, requires_grad=True)
+    r = O.render_view(params, fields, cam, O.TRAIN, return_stats=True)
+    knife = knife_mask(r, O.TRAIN).reshape(H, W)
+    w = torch.from_numpy(w_img).double() * (~knife).double()[None]
+    L = torch.sum(r["rgb"].T.reshape(3, H, W) * w)
+    leaves = [params.pos, params.opac_e, fields.table_rad] + list(fields.mlp_geo) + list(fields.mlp_col)
+    gs = torch.autograd.grad(L, leaves, allow_unused=True)
+    ref = dict(pos=gs[0], opac_e=gs[1], table_rad=gs[2],
+               mlp_geo=torch.cat([g.reshape(-1) for g in gs[3:3 + len(fields.mlp_geo)]]),
+               mlp_col=torch.cat([g.reshape(-1) for g in gs[3 + len(fields.mlp_geo):]]))
+    ds = _device_single(scene)
+    st = P.render(ds, cams, P.TRAIN)
+    dL = torch.from_numpy(w.float().numpy()).cuda()[None].contiguous()
+    z = torch.zeros_like
+    grads = dict(pos=z(ds.pos), scale_e=z(ds.scale_e), rot_e=z(ds.rot_e), opac_e=z(ds.opac_e), col_e=z(ds.col_e),
+                 table_geo=torch.full(ds.table_rad.shape, 7.0, device="cuda"), table_rad=z(ds.table_rad),
+                 mlp_geo=z(ds.mlp_geo), mlp_col=z(ds.mlp_col))
+    P.render_backward(ds, cams, st, dL, grads=grads)
+    torch.cuda.synchronize()
+    errs = {}
+    for k, rr in ref.items():
+        g = grads[k].detach().cpu().double()
+        g = g.T if k == "pos" else g
+        errs[k] = float((g - rr.reshape(g.shape)).norm() / rr.norm())
+    _say("single-field gradient errors", errs)
+    assert all(e < 1e-3 for e in errs.values()), errs
+    # the ignored geometry-table gradient buffer is untouched
+    assert bool((grads["table_geo"] == 7.0).all())
