@@ -180,7 +180,7 @@ def main():
         e.record()
         ev.setdefault(name, []).append(e)
 
-    def train_step(ev=None, dssim=False):
+    def train_step(ev=None, dssim=False, overlap=True):
         st = P.render(ds, cams, P.TRAIN, ws=ws, events=ev)
         if dssim:
             loss, dL = P.l1_dssim_loss(st.image, target, lam=0.2, ws=ws)
@@ -191,7 +191,7 @@ def main():
                 t.zero_()
         if ev is not None:
             mark(ev, "bwd0")
-        P.render_backward(ds, cams, st, dL, grads=grads, ws=ws, events=ev)
+        P.render_backward(ds, cams, st, dL, grads=grads, ws=ws, events=ev, overlap=overlap)
         if ev is not None:
             mark(ev, "bwd1")
         return st, loss
@@ -216,13 +216,24 @@ def main():
         ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
         print(json.dumps({"render_ms": round(ms_render, 4), "stages": stages(ev_r, fwd_keys)}), flush=True)
         return
+    # headline: the adjoint's Gaussian and background branches on two streams
     ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
     bwd_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage0", "bwd_stage1"),
-                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_stage3"),
-                ("bwd_bg_tables", "bwd_stage3", "bwd_stage4"))
+                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_gauss_end"),
+                ("bwd_bg_decoders", "bwd_stage3", "bwd_stage4"), ("bwd_bg_tables", "bwd_stage4", "bwd_bg_end"),
+                ("bwd_dw", "bwd_stage5", "bwd_stage6"))
     st_train = stages(ev_t, fwd_keys + bwd_keys)
-    print(f"[bench] train step {ms_train:.3f} ms; stages {st_train}; loss {float(loss):.5f}; "
+    print(f"[bench] train step {ms_train:.3f} ms; stages (branches overlapped) {st_train}; loss {float(loss):.5f}; "
           f"entries {st.n_entries}", file=sys.stderr, flush=True)
+    # the same step with every stage alone on one stream: per-kernel times
+    ms_train_serial, ev_s, _ = timed(lambda ev: train_step(ev, overlap=False), args.steps)
+    ser_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage0", "bwd_stage1"),
+                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_stage3"),
+                ("bwd_bg_decoders", "bwd_stage3", "bwd_stage4"), ("bwd_bg_tables", "bwd_stage4", "bwd_stage5"),
+                ("bwd_dw", "bwd_stage5", "bwd_stage6"))
+    st_serial = stages(ev_s, fwd_keys + ser_keys)
+    print(f"[bench] train step, stages serial {ms_train_serial:.3f} ms; stages {st_serial}", file=sys.stderr,
+          flush=True)
     # the paper's full training loss: (1 - 0.2) L1 + 0.2 D-SSIM (fused kernel)
     ms_train_ds, _, _ = timed(lambda ev: train_step(ev, dssim=True), args.steps)
     img_t = st.image.contiguous()
@@ -294,12 +305,12 @@ def main():
 
     # Roofline of the dominant kernel of the train step: the background
     # points' radiance-table adjoint (k_bg_grid_bwd, alone in backward stage
-    # 3).  Algorithmic bytes per background pixel: its feature gradient read
+    # 4 of the serial run).  Algorithmic bytes per background pixel: its feature gradient read
     # (2L floats) + for each of L levels x 8 corners one read-modify-write of
     # the 2-float table row (16 B).
     n_bg = V * H * W
     per_px = 2 * cfg.levels * 4 + cfg.levels * 8 * 16
-    bg_ms = st_train["bwd_bg_tables"]
+    bg_ms = st_serial["bwd_bg_tables"]
     ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
     roof = {"kernel": "k_bg_grid_bwd", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_bg_grid_bwd"),
@@ -331,6 +342,8 @@ def main():
            "train_step_ms": round(ms_train, 4), "render_ms": round(ms_render, 4),
            "render_fps": round(1000.0 / ms_render, 2),
            "stage_ms_train": {k: round(v, 4) for k, v in st_train.items()},
+           "train_step_serial_ms": round(ms_train_serial, 4),
+           "stage_ms_train_serial": {k: round(v, 4) for k, v in st_serial.items()},
            "stage_ms_render": {k: round(v, 4) for k, v in st_render.items()},
            "variant_f16_bf16": {"render_ms": round(ms_render_v, 4), "render_fps": round(1000.0 / ms_render_v, 2),
                                 "stage_ms_render": {k: round(v, 4) for k, v in st_render_v.items()},

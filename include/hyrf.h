@@ -245,17 +245,21 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
                                  const hyrf_grads* grads, void* ws, size_t ws_bytes,
                                  void* stream);
 
-/* The same adjoint split into its four stages, for callers that interleave
- * or time them.  Call stage 0, 1, 2, 3 in order on one stream with the same
- * arguments and workspace (each stage reads what the previous ones left in
- * the workspace):
- *   0  blending and projection adjoints (explicit-parameter gradients)
- *   1  decoder adjoints of the Gaussians and of the background points
- *      (decoder weight gradients, view-direction part of dL/dp)
- *   2  hash-table adjoint of the Gaussians (table gradients, dL/dp through
- *      the interpolation weights and the contraction)
- *   3  radiance-table adjoint of the background points.
- * hyrf_render_backward == stages 0..3. */
+/* The same adjoint split into six stages, for callers that overlap or time
+ * them.  Every stage takes the same arguments and workspace; each reads what
+ * the stages it depends on left in the workspace:
+ *   0  blending and projection adjoints (explicit-parameter gradients,
+ *      densification statistics); permutes the decoder weights
+ *   1  decoder adjoints of the Gaussians                          (after 0)
+ *   2  hash-table adjoint of the Gaussians: table gradients, dL/dp through
+ *      the interpolation weights and the contraction               (after 1)
+ *   3  colour-decoder adjoint of the background points             (after 0)
+ *   4  radiance-table adjoint of the background points             (after 3)
+ *   5  decoder weight gradients from the partials of 1 and 3   (after 1, 3)
+ * The Gaussian branch (1, 2) and the background branch (3, 4) touch disjoint
+ * workspace regions and meet only in atomic additions to the radiance-table
+ * gradient, so they may run concurrently on two streams (the caller orders
+ * them with events).  hyrf_render_backward == stages 0..5 on one stream. */
 hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields, const hyrf_gaussians* g,
                                        const hyrf_camera* cams, int32_t n_views,
                                        const hyrf_fwd_state* saved, const float* dL_drgb,

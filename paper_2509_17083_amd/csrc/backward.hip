@@ -9,9 +9,12 @@
 //                   projection adjoint (no atomics: one lane per Gaussian).
 //  k_field_bwd      per 16 Gaussians per wave (or 16 background pixels):
 //                   decoder adjoints on MFMA with dW accumulated through LDS
-//                   staging, hash-table scatter-add (atomics) and the
-//                   position gradient through the interpolation weights, the
-//                   contraction and the view direction.
+//                   staging; feature gradients out, plus the view-direction
+//                   part of the position gradient.
+//  k_grid_bwd       per Gaussian: hash-table scatter-add (cell runs summed,
+//                   lane-combined atomics) and the position gradient through
+//                   the interpolation weights and the contraction.
+//  k_bg_grid_bwd    per background pixel: radiance-table scatter-add.
 //  k_dw_reduce      sums the per-workgroup dW partials in a fixed order.
 #include "backward.h"
 #include "block.h"
@@ -392,7 +395,6 @@ constexpr int MAP_SLOTS = 2048;
 constexpr int BG_GRID_BLOCKS = 1024;   // persistent: 4 workgroups per CU, each a contiguous pixel band
 constexpr uint32_t MAP_EMPTY = 0xFFFFFFFFu;
 constexpr int MAP_MAX_RES = 182;   // levels up to this resolution use the workgroup map
-constexpr int MAP_SEG_RES = 1383;  // levels up to this resolution pre-reduce runs of equal rows
 
 // Add (v0, v1) to table row `row` of level `lev`: through the workgroup map
 // when `use_map` (linear probing, at most 8 slots), else (or when the probe
@@ -606,73 +608,101 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   write_dw<Sh, ACC>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
-// Add (v0, v1) to row `row` of one table level from every lane of the wave,
-// first summing in registers the lanes that hit the same row (up to 4 distinct
-// rows per call, the rest add alone).  Spatially ordered points share the
-// coarse cells, so one atomic then serves many lanes.  Every lane of the wave
-// must call it (ballots); lanes with nothing to add pass zeros.
-__device__ __forceinline__ void wave_row_add(float* tab, uint32_t row, float v0, float v1, bool reduce) {
+// ---- cell-run scatter of a level's 8 corners x 2 features
+//
+// A float atomic costs one memory request per 64-byte line touched by a wave
+// instruction: lanes of one instruction that hit the same line combine, lanes
+// that hit the same ADDRESS do not, and requests to distinct lines issue at
+// one per clock of the memory-side atomic units.  So the table adjoints (1)
+// sum, in registers, the contributions of consecutive lanes whose points lie
+// in the same grid cell (runs: spatially ordered Gaussians, adjacent pixels),
+// then (2) stage each run total's 16 floats in LDS and issue them 16 lanes
+// per cell, corner-major: corners c and c^1 differ in x only and are adjacent
+// rows whenever the cell's x index is even, so one instruction touches a few
+// lines per cell instead of one line per float.
+constexpr int STAGE_CELLS = 32;   // run totals staged per wave and pass
+
+struct CellStage {
+  uint32_t idx[STAGE_CELLS * 16];
+  float val[STAGE_CELLS * 16];
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Lanes whose cell differs from the previous lane's (lane 0 always).
+__device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
   const int lane = lane_id();
-  if (!reduce) {
-    if (v0 != 0.f) atomicAdd(tab + (size_t)row * 2, v0);
-    if (v1 != 0.f) atomicAdd(tab + (size_t)row * 2 + 1, v1);
-    return;
-  }
-  uint64_t pending = __ballot(v0 != 0.f || v1 != 0.f);
-#pragma unroll 1
-  for (int it = 0; it < 4 && pending; ++it) {
-    const int lead = __ffsll((long long)pending) - 1;
-    const uint32_t key = __shfl(row, lead, 64);
-    const bool mine = ((pending >> lane) & 1ull) && row == key;
-    const float s0 = wave_sum_dpp(mine ? v0 : 0.f);
-    const float s1 = wave_sum_dpp(mine ? v1 : 0.f);
-    if (lane == lead) {
-      if (s0 != 0.f) atomicAdd(tab + (size_t)key * 2, s0);
-      if (s1 != 0.f) atomicAdd(tab + (size_t)key * 2 + 1, s1);
+  const int p0 = __shfl_up(ci[0], 1, 64), p1 = __shfl_up(ci[1], 1, 64), p2 = __shfl_up(ci[2], 1, 64);
+  return __ballot(lane == 0 || p0 != ci[0] || p1 != ci[1] || p2 != ci[2]);
+}
+
+// Segmented inclusive sums of v over the runs that start at the set bits of
+// `heads`: the last lane of every run ends with the run's totals.
+template <int N>
+__device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
+  if (heads == ~0ull) return;   // every lane its own run
+  const int lane = lane_id();
+  const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
+  const int head = 63 - __clzll((long long)upto);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const float t = __shfl_up(v[k], off, 64);
+      if (lane - off >= head) v[k] += t;
     }
-    pending &= ~__ballot(mine);
-  }
-  if ((pending >> lane) & 1ull) {
-    if (v0 != 0.f) atomicAdd(tab + (size_t)row * 2, v0);
-    if (v1 != 0.f) atomicAdd(tab + (size_t)row * 2 + 1, v1);
   }
 }
 
-// Segmented sum over runs of equal `row` in consecutive lanes: every lane
-// ends with the sum of its run's values from the run head up to itself, so
-// the last lane of each run holds the run total (Hillis-Steele scan bounded
-// by the run head).  Returns true in the lanes that hold a run total.
+// Add the run totals of one level to a table-gradient level g ([T][2]):
+// the last lane of each run holds 16 floats, row[c] * 2 + f <- v[2c + f].
 // Every lane of the wave must call it.
-__device__ __forceinline__ bool wave_run_sum(uint32_t row, float& v0, float& v1) {
+__device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t heads, const uint32_t (&row)[8],
+                                              const float* v, CellStage& st) {
   const int lane = lane_id();
-  const uint32_t prev = __shfl_up(row, 1, 64);
-  const uint32_t next = __shfl_down(row, 1, 64);
-  int head = (lane == 0 || prev != row) ? lane : 0;
+  const uint64_t tails = (heads >> 1) | (1ull << 63);
+  const bool tail = (tails >> lane) & 1ull;
+  const int rank = __popcll(tails & ((1ull << lane) - 1ull));
+  const int K = __popcll(tails);
+  for (int b = 0; b < K; b += STAGE_CELLS) {
+    if (tail && rank >= b && rank < b + STAGE_CELLS) {
+      const int base = (rank - b) * 16;
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const int t = __shfl_up(head, off, 64);
-    if (lane >= off) head = max(head, t);
-  }
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-    const float t0 = __shfl_up(v0, off, 64);
-    const float t1 = __shfl_up(v1, off, 64);
-    if (lane - off >= head) {
-      v0 += t0;
-      v1 += t1;
+      for (int c = 0; c < 8; ++c) {
+        st.idx[base + 2 * c] = row[c] * 2u;
+        st.idx[base + 2 * c + 1] = row[c] * 2u + 1u;
+        st.val[base + 2 * c] = v[2 * c];
+        st.val[base + 2 * c + 1] = v[2 * c + 1];
+      }
     }
+    wave_lds_sync();
+    const int n = min(K - b, STAGE_CELLS) * 16;
+    for (int s2 = lane; s2 < n; s2 += 64) {
+      const float x = st.val[s2];
+      if (x != 0.f) atomicAdd(g + st.idx[s2], x);
+    }
+    wave_lds_sync();
   }
-  return lane == 63 || next != row;
 }
 
-constexpr int GRID_SEG_RES = 182;   // Gaussians: levels up to this resolution pre-reduce equal rows
 
 // Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
 // levels per lane: scatter-add of w_c * dL/df into both tables and
 // dL/dx = sum_c (dL/df . table[c]) dw_c/dx, then the contraction Jacobian ->
 // dL/dp.
+// Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
+// levels per lane: scatter-add of w_c * dL/df into both tables (cell runs of
+// consecutive Gaussians summed first; they share cells at the coarse levels
+// when the Gaussians are stored in spatial order) and
+// dL/dx = sum_c (dL/df . table[c]) dw_c/dx, then the contraction Jacobian ->
+// dL/dp.
 template <class TT>
 __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
+  __shared__ CellStage stage[4];
+  CellStage& st = stage[threadIdx.x / 64];
   const TT* table_geo = (const TT*)a.table_geo;
   const TT* table_rad = (const TT*)a.table_rad;
   const int item = blockIdx.x * 256 + threadIdx.x;
@@ -686,6 +716,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   }
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const bool single = a.grid.single != 0;
+  const bool do_geo = a.g_table_geo && !single;
   double x[3];
   contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
   float dxv[3] = {0.f, 0.f, 0.f};
@@ -709,7 +740,6 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       dg = make_float2(0.f, 0.f);
     }
     const float fres = (float)res;
-    const bool reduce = res <= GRID_SEG_RES;
     uint32_t rg[8], rr[8];
     float2 vg[8], vr[8];
 #pragma unroll
@@ -721,6 +751,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       vg[c] = valid && !single ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
       vr[c] = valid ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
     }
+    float sg[16], sr[16];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
       const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
@@ -728,13 +759,23 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       const float wy = by ? wv[1] : 1.f - wv[1];
       const float wz = bz ? wv[2] : 1.f - wv[2];
       const float wc = (wx * wy) * wz;
-      if (a.g_table_geo && !single)
-        wave_row_add(a.g_table_geo + (size_t)lev * Tg * 2, rg[c], wc * dg.x, wc * dg.y, reduce);
-      if (a.g_table_rad) wave_row_add(a.g_table_rad + (size_t)lev * Tr * 2, rr[c], wc * dr.x, wc * dr.y, reduce);
+      sg[2 * c] = wc * dg.x;
+      sg[2 * c + 1] = wc * dg.y;
+      sr[2 * c] = wc * dr.x;
+      sr[2 * c + 1] = wc * dr.y;
       const float val = (dg.x * vg[c].x + dg.y * vg[c].y) + (dr.x * vr[c].x + dr.y * vr[c].y);
       dxv[0] += val * fres * (bx ? 1.f : -1.f) * (wy * wz);
       dxv[1] += val * fres * (by ? 1.f : -1.f) * (wx * wz);
       dxv[2] += val * fres * (bz ? 1.f : -1.f) * (wx * wy);
+    }
+    const uint64_t heads = cell_heads(ci);
+    if (do_geo) {
+      run_sums<16>(heads, sg);
+      scatter_tails(a.g_table_geo + (size_t)lev * Tg * 2, heads, rg, sg, st);
+    }
+    if (a.g_table_rad) {
+      run_sums<16>(heads, sr);
+      scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, rr, sr, st);
     }
   }
   if (valid && a.g_pos) {
@@ -745,16 +786,17 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   }
 }
 
-// Hash-grid adjoint of the background points (radiance table only; the
-// sphere points do not depend on parameters).  One lane per pixel, 64
-// consecutive pixels of a row per wave, all levels per lane.  Equal rows
-// among the wave's pixels are summed in registers first (runs of consecutive
-// pixels share the coarse cells); the coarsest levels then go through a
-// workgroup-private map that each persistent workgroup flushes once, the
-// finer ones straight to global atomics.
+// Radiance-table adjoint of the background points (Sec. 3.3): one lane per
+// pixel, 64 consecutive pixels of a row per wave, all levels per lane.  Runs
+// of consecutive pixels in the same cell are summed in registers first; the
+// coarsest levels then go through a workgroup-private map that each
+// persistent workgroup flushes once, the finer ones through the cell-staged
+// scatter.
 __global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
   __shared__ uint32_t map_key[MAP_SLOTS];
   __shared__ float2 map_val[MAP_SLOTS];
+  __shared__ CellStage stage[4];
+  CellStage& st = stage[threadIdx.x / 64];
   for (int k = threadIdx.x; k < MAP_SLOTS; k += 256) {
     map_key[k] = MAP_EMPTY;
     map_val[k] = make_float2(0.f, 0.f);
@@ -787,17 +829,27 @@ __global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
       const bool drn = (a.grid.dense_rad >> lev) & 1u;
       float2 df = make_float2(0.f, 0.f);
       if (valid) df = *reinterpret_cast<const float2*>(a.dfeat_bg + (size_t)pix * 2 * a.grid.L + 2 * lev);
-      const bool use_map = res <= MAP_MAX_RES;
+      uint32_t row[8];
+      float sv[16];
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
         const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
-        const uint32_t row = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
-                                        a.grid.mask_rad);
-        float v0 = wc * df.x, v1 = wc * df.y;
-        // consecutive pixels of a row share the corner rows of a cell:
-        // one add per run of equal rows (no colliding lanes in an atomic)
-        if (wave_run_sum(row, v0, v1)) map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row, v0, v1, use_map);
+        row[c] = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
+                            a.grid.mask_rad);
+        sv[2 * c] = wc * df.x;
+        sv[2 * c + 1] = wc * df.y;
+      }
+      const uint64_t heads = cell_heads(ci);
+      run_sums<16>(heads, sv);
+      if (res <= MAP_MAX_RES) {
+        const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+        if (tail)
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row[c], sv[2 * c], sv[2 * c + 1], true);
+      } else {
+        scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, row, sv, st);
       }
     }
   }
@@ -842,16 +894,23 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
   FieldBwdArgs a = L.field;
   a.wf_geo = L.wf_geo; a.wf_col = L.wf_col; a.wb_geo = L.wb_geo; a.wb_col = L.wb_col;
   a.n_w = Sh::N_GEO + Sh::N_COL;
-  if (L.stages & BWD_STAGE_DECODERS) {
+  if (L.stages & BWD_STAGE_SPLATS) {
+    // per-splat gradient records, then the projection adjoint; the decoder
+    // weights are permuted here so that both decoder stages can follow
+    k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
+    dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
+    k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
+    k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
     k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
-    k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
-    int parts = L.blocks_g;
-    if (L.with_bg) {
-      FieldBwdArgs b = a;
-      b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
-      k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
-      parts += L.blocks_r;
-    }
+  }
+  if (L.stages & BWD_STAGE_DECODERS) k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+  if ((L.stages & BWD_STAGE_BG_DECODERS) && L.with_bg) {
+    FieldBwdArgs b = a;
+    b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
+    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
+  }
+  if (L.stages & BWD_STAGE_DW) {
+    const int parts = L.blocks_g + (L.with_bg ? L.blocks_r : 0);
     k_dw_reduce<<<(unsigned)((a.n_w + 63) / 64), 256, 0, st>>>(a.dw_part, parts, a.n_w, L.g_mlp_geo, L.g_mlp_col,
                                                                Sh::N_GEO);
   }
@@ -884,14 +943,6 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
 }
 
 void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st) {
-  if (L.stages & BWD_STAGE_SPLATS) {
-    // per-splat gradient records, then the projection adjoint
-    k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
-    dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
-    k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
-    k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
-  }
-  if (!(L.stages & (BWD_STAGE_DECODERS | BWD_STAGE_TABLES | BWD_STAGE_BG_TABLES))) return;
   if (Lv == 16 && hid == 64 && nh == 2) {
     using Sh = Shape<16, 64, 2>;
     if (!L.f16 && !L.bf) return launch_bwd_t<Sh, float, false>(L, st);

@@ -177,6 +177,14 @@ class Workspace:
     def __init__(self):
         self.bufs: Dict[str, torch.Tensor] = {}
 
+    def side_stream(self) -> torch.cuda.Stream:
+        """A second stream (default priority) for work that overlaps the
+        caller's stream."""
+        st = getattr(self, "_side", None)
+        if st is None:
+            st = self._side = torch.cuda.Stream()
+        return st
+
     def get(self, name: str, nbytes: int) -> torch.Tensor:
         b = self.bufs.get(name)
         if b is None or b.numel() < nbytes:
@@ -282,10 +290,10 @@ def composite(scene: Optional[DeviceScene], cams, splats_c, vals, ranges, mode: 
     return img, T, last, bg
 
 
-def _mark(events, name):
+def _mark(events, name, stream=None):
     if events is not None:
         e = torch.cuda.Event(enable_timing=True)
-        e.record()
+        e.record(stream)
         events.setdefault(name, []).append(e)
 
 
@@ -345,10 +353,11 @@ def l1_dssim_loss(img: torch.Tensor, target: torch.Tensor, lam: float = 0.2, gra
 
 def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.Tensor,
                     grads: Optional[Dict[str, torch.Tensor]] = None, ws: Optional[Workspace] = None,
-                    events: Optional[dict] = None):
+                    events: Optional[dict] = None, overlap: bool = True):
     """Adjoint of a TRAIN-mode `render`: accumulates (+=) gradients of every
     explicit parameter, both tables and both decoders into `grads` (zeroed
-    here when not given).  dL_drgb: (V, 3, H, W) float32."""
+    here when not given).  dL_drgb: (V, 3, H, W) float32.  overlap: run the
+    Gaussian and background branches of the adjoint on two streams."""
     lib = A.load()
     ws = ws or Workspace()
     if st.mode != TRAIN:
@@ -370,18 +379,48 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
     nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1), cams[0].width, cams[0].height)
     w = ws.get("backward", nb)
-    if events is None:
-        A.check("hyrf_render_backward",
-                lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL), C.byref(cg),
-                                         _p(w), w.numel(), _stream()))
-        return grads
-    # stage by stage, with events between the stages
-    for stage in range(4):
-        _mark(events, f"bwd_stage{stage}")
+    def stage(k, stream):
         A.check("hyrf_render_backward_stage",
-                lib.hyrf_render_backward_stage(stage, C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL),
-                                               C.byref(cg), _p(w), w.numel(), _stream()))
-    _mark(events, "bwd_stage4")
+                lib.hyrf_render_backward_stage(k, C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL),
+                                               C.byref(cg), _p(w), w.numel(), C.c_void_p(stream.cuda_stream)))
+
+    if not overlap:
+        if events is None:
+            A.check("hyrf_render_backward",
+                    lib.hyrf_render_backward(C.byref(f), C.byref(g), cc, len(cams), C.byref(fs), _p(dL),
+                                             C.byref(cg), _p(w), w.numel(), _stream()))
+            return grads
+        main = torch.cuda.current_stream()
+        for k in range(6):
+            _mark(events, f"bwd_stage{k}")
+            stage(k, main)
+        _mark(events, "bwd_stage6")
+        return grads
+    # two streams: the Gaussian branch (stages 1, 2) on the caller's stream,
+    # the background branch (stages 3, 4) on a side stream, joined before 5
+    main = torch.cuda.current_stream()
+    side = ws.side_stream()
+    _mark(events, "bwd_stage0")
+    stage(0, main)
+    e0 = torch.cuda.Event()
+    e0.record(main)
+    side.wait_event(e0)
+    _mark(events, "bwd_stage1")
+    stage(1, main)
+    _mark(events, "bwd_stage2")
+    stage(2, main)
+    _mark(events, "bwd_gauss_end")
+    _mark(events, "bwd_stage3", side)
+    stage(3, side)
+    _mark(events, "bwd_stage4", side)
+    stage(4, side)
+    _mark(events, "bwd_bg_end", side)
+    e1 = torch.cuda.Event()
+    e1.record(side)
+    main.wait_event(e1)
+    _mark(events, "bwd_stage5")
+    stage(5, main)
+    _mark(events, "bwd_stage6")
     return grads
 
 

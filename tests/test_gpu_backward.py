@@ -132,9 +132,11 @@ def test_staged_backward_equals_one_call():
     ds = device_scene(scene)
     st = P.render(ds, cams, P.TRAIN)
     dL = torch.from_numpy(hi.make_target_image((1, 3, 64, 64), seed=8) - 0.5).cuda()
-    g1 = P.render_backward(ds, cams, st, dL)
-    g2 = P.render_backward(ds, cams, st, dL, events={})
+    g1 = P.render_backward(ds, cams, st, dL, overlap=False)              # one C call
+    g2 = P.render_backward(ds, cams, st, dL, overlap=False, events={})   # six stages, one stream
+    g3 = P.render_backward(ds, cams, st, dL, overlap=True)               # two branches, two streams
     torch.cuda.synchronize()
     for k, v in g1.items():
         if v is not None:
-            assert torch.allclose(g2[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
+            for g in (g2, g3):
+                assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
