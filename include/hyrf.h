@@ -181,6 +181,9 @@ typedef struct {
   const float* T_final;          /* [V][H][W] from hyrf_composite                 */
   const int32_t* last;           /* [V][H][W] from hyrf_composite                 */
   const float* bg_rgb;           /* [V][3][H][W] background colours c_s           */
+  const float* bg_feat;          /* [V*H*W][2L] radiance features of the sphere
+                                    points from hyrf_composite, or NULL (the
+                                    backward then gathers them again)           */
 } hyrf_fwd_state;
 
 /* ---- the render step ------------------------------------------------------ */
@@ -225,13 +228,16 @@ hyrf_status hyrf_bin_sort(const hyrf_splats* splats, const hyrf_camera* cams,
  * ray / sphere intersection, PE(ray direction))) (Sec. 3.3 Eqs. 10-11).
  * out_rgb [V][3][H][W]; out_T [V][H][W]; in TRAIN mode out_last [V][H][W]
  * (entries consumed up to the last contributor) and out_bg [V][3][H][W] are
- * required, in RENDER mode they may be NULL.  ws: at least
+ * required, in RENDER mode they may be NULL.  out_bg_feat (TRAIN mode,
+ * nullable): [V*H*W][2L] float32 radiance features of every sphere point,
+ * kept for the backward (hyrf_fwd_state.bg_feat) so that it need not gather
+ * them again.  ws: at least
  * hyrf_composite_workspace_bytes(V, W, H) bytes. */
 hyrf_status hyrf_composite(const hyrf_splats* splats, const uint32_t* vals,
                            const uint32_t* tile_ranges, const hyrf_camera* cams,
                            int32_t n_views, const hyrf_fields* fields, int32_t mode,
                            float* out_rgb, float* out_T, int32_t* out_last, float* out_bg,
-                           void* ws, size_t ws_bytes, void* stream);
+                           float* out_bg_feat, void* ws, size_t ws_bytes, void* stream);
 
 /* Adjoint of the whole step: given dL/dC [V][3][H][W], accumulates (+=) the
  * gradients of every explicit parameter, both hash tables (background uses

@@ -66,7 +66,7 @@ ADAM_MAX_GROUPS = 16
 
 class hyrf_fwd_state(C.Structure):
     _fields_ = [("query", C.POINTER(hyrf_query_out)), ("splats", C.POINTER(hyrf_splats)),
-                ("vals", P), ("tile_ranges", P), ("T_final", P), ("last", P), ("bg_rgb", P)]
+                ("vals", P), ("tile_ranges", P), ("T_final", P), ("last", P), ("bg_rgb", P), ("bg_feat", P)]
 
 
 EXPORTS = {
@@ -77,7 +77,7 @@ EXPORTS = {
     "hyrf_bin_sort": (C.c_int, [C.POINTER(hyrf_splats), C.POINTER(hyrf_camera), C.c_int32, C.c_int64,
                                 C.c_int64, P, P, P, P, C.c_size_t, P]),
     "hyrf_composite": (C.c_int, [C.POINTER(hyrf_splats), P, P, C.POINTER(hyrf_camera), C.c_int32,
-                                 C.POINTER(hyrf_fields), C.c_int32, P, P, P, P, P, C.c_size_t, P]),
+                                 C.POINTER(hyrf_fields), C.c_int32, P, P, P, P, P, P, C.c_size_t, P]),
     "hyrf_render_backward": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians), C.POINTER(hyrf_camera),
                                        C.c_int32, C.POINTER(hyrf_fwd_state), P, C.POINTER(hyrf_grads), P,
                                        C.c_size_t, P]),

@@ -284,6 +284,7 @@ size_t hyrf_composite_workspace_bytes(int32_t n_views, int32_t width, int32_t he
 hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const uint32_t* tile_ranges,
                            const hyrf_camera* cams, int32_t n_views, const hyrf_fields* fields,
                            int32_t mode, float* out_rgb, float* out_T, int32_t* out_last, float* out_bg,
+                           float* out_bg_feat,
                            void* ws, size_t ws_bytes, void* stream) {
   hyrf_status s;
   if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
@@ -331,6 +332,7 @@ hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const ui
     b.T = out_T;
     b.out_rgb = out_rgb;
     b.bg_save = mode == HYRF_TRAIN ? out_bg : nullptr;
+    b.feat_save = mode == HYRF_TRAIN ? out_bg_feat : nullptr;
     launch_bg(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype,
               fields->mlp_dtype == HYRF_BF16, b, n_views * W * H, st);
   }
@@ -444,6 +446,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   L.comp.T_final = saved->T_final;
   L.comp.last = saved->last;
   L.comp.bg = saved->bg_rgb;
+  L.field.bg_feat = saved->bg_feat;
   L.comp.dL = dL_drgb;
   L.comp.gs = w.gs;
   L.n_gs = (int64_t)n_views * sp->n_max * 9;

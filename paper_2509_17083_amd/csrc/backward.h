@@ -79,6 +79,7 @@ struct FieldBwdArgs {
   int W, H;
   const float* T_final;
   const float* dL;
+  const float* bg_feat;  // [V*H*W][2L] saved background features, or NULL (gather)
 };
 
 struct GridBwdArgs {

@@ -4,7 +4,7 @@
 //                   with the background term, transmittance recovered by
 //                   division from the final value; per-splat gradients of
 //                   (u, v, conic, opacity, rgb) summed over each wave's 64
-//                   pixels, then one atomic per value and wave.
+//                   pixels, then added by 9 lanes of one atomic instruction.
 //  k_project_bwd    per surviving Gaussian, looping over views: EWA
 //                   projection adjoint (no atomics: one lane per Gaussian).
 //  k_field_bwd      per 16 Gaussians per wave (or 16 background pixels):
@@ -123,14 +123,14 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
         gu = wave_sum_dpp(gu); gv = wave_sum_dpp(gv); ga = wave_sum_dpp(ga);
         gb = wave_sum_dpp(gb); gc = wave_sum_dpp(gc); go = wave_sum_dpp(go);
         gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gbb = wave_sum_dpp(gbb);
-        if (lane_id() == 0) {
-          const uint32_t id = sid[k];
-          if (id < a.n_rec) {
-            float* o = a.gs + (size_t)id * GS;
-            atomicAdd(o + 0, gu); atomicAdd(o + 1, gv); atomicAdd(o + 2, ga);
-            atomicAdd(o + 3, gb); atomicAdd(o + 4, gc); atomicAdd(o + 5, go);
-            atomicAdd(o + 6, gr); atomicAdd(o + 7, gg); atomicAdd(o + 8, gbb);
-          }
+        // the record's 9 floats from lanes 0..8 in one instruction: one or
+        // two 64-byte lines, so the atomics combine into one or two requests
+        const int ln = lane_id();
+        const uint32_t id = sid[k];
+        if (ln < GS && id < a.n_rec) {
+          const float val = ln == 0 ? gu : ln == 1 ? gv : ln == 2 ? ga : ln == 3 ? gb : ln == 4 ? gc
+                          : ln == 5 ? go : ln == 6 ? gr : ln == 7 ? gg : gbb;
+          atomicAdd(a.gs + (size_t)id * GS + ln, val);
         }
       }
     }
@@ -515,8 +515,18 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       const int yy = rem / a.W, xx = rem - yy * a.W;
       double ps[3], d[3];
       sphere_point_f64(a.cams.c[v_r], xx, yy, (double)a.grid.bg_radius, ps, d);
-      contract_f64(a.grid, ps[0], ps[1], ps[2], x);
-      gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, (const TT*)a.table_rad, fg, fr, nullptr, nullptr);
+      if (a.bg_feat) {
+        // features saved by the forward
+#pragma unroll
+        for (int k = 0; k < Sh::L / 4; ++k) {
+          const float2 f2 = *reinterpret_cast<const float2*>(a.bg_feat + (size_t)pix * 2 * Sh::L + 2 * (g + 4 * k));
+          fr[2 * k] = f2.x;
+          fr[2 * k + 1] = f2.y;
+        }
+      } else {
+        contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+        gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, (const TT*)a.table_rad, fg, fr, nullptr, nullptr);
+      }
       const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
       pxf = (float)(d[0] / dn); pyf = (float)(d[1] / dn); pzf = (float)(d[2] / dn);
       if (!valid) {

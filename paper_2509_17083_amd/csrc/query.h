@@ -42,6 +42,7 @@ struct BgArgs {
   const float* T;              // [V][H][W] final transmittance
   float* out_rgb;              // [V][3][H][W]: C_fg in, C_fg + T c_s out
   float* bg_save;              // [V][3][H][W] c_s, or NULL
+  float* feat_save;            // [V*H*W][2L] radiance features of the sphere points, or NULL
 };
 
 bool shape_supported(int L, int hid, int nh);

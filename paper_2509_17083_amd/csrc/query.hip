@@ -191,6 +191,12 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
       xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
     v4f o;
     M::template run<M::SC>(w_col, xc, o, lane);
+    if (a.feat_save && valid) {
+#pragma unroll
+      for (int k = 0; k < Sh::L / 4; ++k)
+        *reinterpret_cast<float2*>(a.feat_save + (size_t)pix * 2 * Sh::L + 2 * (g + 4 * k)) =
+            make_float2(fr[2 * k], fr[2 * k + 1]);
+    }
     if (g == 0 && valid) {
       const float T = a.T[pix];
 #pragma unroll

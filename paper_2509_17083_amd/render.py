@@ -209,6 +209,7 @@ class ForwardState:
     T: torch.Tensor         # (V, H, W)
     last: Optional[torch.Tensor]
     bg: Optional[torch.Tensor]
+    bg_feat: Optional[torch.Tensor] = None   # (V*H*W, 2L) background-point features (TRAIN)
     c: Dict[str, object] = field(default_factory=dict)   # ctypes structs kept alive
 
 
@@ -272,7 +273,7 @@ def bin_sort(cams, splats_c, n_max: int, n_entries: int, want_keys: bool = False
 
 
 def composite(scene: Optional[DeviceScene], cams, splats_c, vals, ranges, mode: int,
-              ws: Optional[Workspace] = None):
+              ws: Optional[Workspace] = None, keep_bg_feat: bool = True):
     lib = A.load()
     ws = ws or Workspace()
     V, W, H = len(cams), cams[0].width, cams[0].height
@@ -280,14 +281,17 @@ def composite(scene: Optional[DeviceScene], cams, splats_c, vals, ranges, mode: 
     T = torch.empty(V, H, W, device="cuda")
     last = torch.empty(V, H, W, dtype=torch.int32, device="cuda") if mode == TRAIN else None
     bg = torch.empty(V, 3, H, W, device="cuda") if (mode == TRAIN and scene is not None) else None
+    # background-point features kept for the backward (TRAIN mode)
+    bg_feat = (torch.empty(V * H * W, 2 * scene.levels, device="cuda")
+               if (mode == TRAIN and scene is not None and keep_bg_feat) else None)
     nb = lib.hyrf_composite_workspace_bytes(V, W, H)
     w = ws.get("composite", nb)
     cc = c_cameras(cams)
     f = scene.c_fields() if scene is not None else None
     A.check("hyrf_composite", lib.hyrf_composite(C.byref(splats_c), _p(vals), _p(ranges), cc, V,
                                                  C.byref(f) if f is not None else None, mode, _p(img), _p(T),
-                                                 _p(last), _p(bg), _p(w), w.numel(), _stream()))
-    return img, T, last, bg
+                                                 _p(last), _p(bg), _p(bg_feat), _p(w), w.numel(), _stream()))
+    return img, T, last, bg, bg_feat
 
 
 def _mark(events, name, stream=None):
@@ -314,10 +318,10 @@ def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = Fal
     _mark(events, "bin0")
     keys, vals, ranges = bin_sort(cams, spc, max(scene.n, 1), n_entries, want_keys, ws)
     _mark(events, "bin1")
-    img, T, last, bg = composite(scene, cams, spc, vals, ranges, mode, ws)
+    img, T, last, bg, bg_feat = composite(scene, cams, spc, vals, ranges, mode, ws)
     _mark(events, "composite1")
     return ForwardState(mode=mode, V=V, W=W, H=H, n_entries=n_entries, query=q, splats=sp, vals=vals,
-                        keys=keys, ranges=ranges, image=img, T=T, last=last, bg=bg,
+                        keys=keys, ranges=ranges, image=img, T=T, last=last, bg=bg, bg_feat=bg_feat,
                         c=dict(qout=qout, splats=spc))
 
 
@@ -375,7 +379,8 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
                          "mlp_col", "dens_accum", "dens_count")])
     qout, spc = st.c["qout"], st.c["splats"]
     fs = A.hyrf_fwd_state(C.pointer(qout), C.pointer(spc), st.vals.data_ptr(), st.ranges.data_ptr(),
-                          st.T.data_ptr(), st.last.data_ptr(), st.bg.data_ptr())
+                          st.T.data_ptr(), st.last.data_ptr(), st.bg.data_ptr(),
+                          None if st.bg_feat is None else st.bg_feat.data_ptr())
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
     nb = lib.hyrf_backward_workspace_bytes(C.byref(f), len(cams), max(scene.n, 1), cams[0].width, cams[0].height)
     w = ws.get("backward", nb)

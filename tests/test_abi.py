@@ -110,11 +110,12 @@ def test_composite_rejects_bad_mode_and_missing_train_outputs():
     A, lib = _lib()
     sp = A.hyrf_splats(10, 0x1000, 0x2000, 0x3000, 0x4000, 0x5000)
     args = [C.byref(sp), C.c_void_p(0x100), C.c_void_p(0x200), _cam(A), 1, None]
-    st = lib.hyrf_composite(*args, 5, C.c_void_p(0x300), C.c_void_p(0x400), None, None, C.c_void_p(0x500), 1 << 30, None)
+    st = lib.hyrf_composite(*args, 5, C.c_void_p(0x300), C.c_void_p(0x400), None, None, None, C.c_void_p(0x500),
+                            1 << 30, None)
     assert st == A.HYRF_ERR_INVALID_ARGUMENT and "mode" in lib.hyrf_last_error().decode()
     f = _fields(A)
     args[-1] = C.byref(f)
-    st = lib.hyrf_composite(*args, A.HYRF_TRAIN, C.c_void_p(0x300), C.c_void_p(0x400), None, None,
+    st = lib.hyrf_composite(*args, A.HYRF_TRAIN, C.c_void_p(0x300), C.c_void_p(0x400), None, None, None,
                             C.c_void_p(0x500), 1 << 30, None)
     assert st == A.HYRF_ERR_INVALID_ARGUMENT
 

@@ -135,8 +135,10 @@ def test_staged_backward_equals_one_call():
     g1 = P.render_backward(ds, cams, st, dL, overlap=False)              # one C call
     g2 = P.render_backward(ds, cams, st, dL, overlap=False, events={})   # six stages, one stream
     g3 = P.render_backward(ds, cams, st, dL, overlap=True)               # two branches, two streams
+    import dataclasses
+    g4 = P.render_backward(ds, cams, dataclasses.replace(st, bg_feat=None), dL)  # background features gathered again
     torch.cuda.synchronize()
     for k, v in g1.items():
         if v is not None:
-            for g in (g2, g3):
+            for g in (g2, g3, g4):
                 assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
