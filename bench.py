@@ -130,6 +130,8 @@ def main():
                     help="only run a plain 256 MiB device copy (torch) 5 times: the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
     ap.add_argument("--render-only", action="store_true", help="time only the render-mode forward")
+    ap.add_argument("--fp32-only", action="store_true",
+                    help="time only the float32 train step and render (no variants; for profiler runs)")
     ap.add_argument("--layout", choices=["morton", "seeded"], default="morton",
                     help="storage order of the Gaussians: Morton order (the library's spatial_order, applied "
                          "once before timing) or the generator's seeded order")
@@ -244,6 +246,12 @@ def main():
     ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
     st_render = stages(ev_r, fwd_keys)
     print(f"[bench] render {ms_render:.3f} ms/frame; stages {st_render}", file=sys.stderr, flush=True)
+
+    if args.fp32_only:
+        print(json.dumps({"train_step_ms": round(ms_train, 4), "train_step_serial_ms": round(ms_train_serial, 4),
+                          "render_ms": round(ms_render, 4), "stage_ms_train_serial": st_serial,
+                          "stage_ms_render": st_render}), flush=True)
+        return
 
     # precision variant: float16 tables, bfloat16 decoder operands
     dv = ds.with_precision(P.F16, P.BF16)

@@ -134,6 +134,13 @@ typedef struct {
   float* feat_rad;       /* [n][2L] encoded radiance features, or NULL (TRAIN needs it) */
   uint32_t* dbg_index;   /* optional [n][2][L][8] table rows (field 0 = geometry,
                             corner k = dx + 2 dy + 4 dz), or NULL                    */
+  float* feat_jac;       /* optional (TRAIN) [n][L][12] spatial derivatives of the
+                            encoded features with respect to the contracted
+                            position x: per level, geometry field then radiance
+                            field, feature 0 then 1, d/dx, d/dy, d/dz.  Kept for the
+                            backward, which then need not gather the tables again
+                            for dL/dp; NULL -> the backward gathers them.  Not
+                            written for 8-bit tables (render-only).                */
 } hyrf_query_out;
 
 /* Per (view, slot) splat records written by hyrf_project and read by

@@ -42,7 +42,7 @@ class hyrf_camera(C.Structure):
 
 class hyrf_query_out(C.Structure):
     _fields_ = [("vis_count", P), ("vis_idx", P), ("opacity", P), ("scale", P), ("quat", P),
-                ("rgb", P), ("feat_geo", P), ("feat_rad", P), ("dbg_index", P)]
+                ("rgb", P), ("feat_geo", P), ("feat_rad", P), ("dbg_index", P), ("feat_jac", P)]
 
 
 class hyrf_splats(C.Structure):

@@ -198,6 +198,7 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     a.feat_geo = out->feat_geo;
     a.feat_rad = out->feat_rad;
     a.dbg = out->dbg_index;
+    a.jac = out->feat_jac;
     launch_query(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype,
                  fields->mlp_dtype == HYRF_BF16, a, g->n, st);
   }
@@ -483,6 +484,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.rot_e = g->rot_e;
   F.feat_geo = q->feat_geo;
   F.feat_rad = q->feat_rad;
+  F.jac = q->feat_jac;
   F.dgeo = w.dgeo;
   F.dcol = w.dcol;
   F.dfeat_geo = w.dfeat_geo;

@@ -80,6 +80,7 @@ struct FieldBwdArgs {
   const float* T_final;
   const float* dL;
   const float* bg_feat;  // [V*H*W][2L] saved background features, or NULL (gather)
+  const float* jac;      // [n][L][12] saved feature derivatives, or NULL
 };
 
 struct GridBwdArgs {
@@ -92,6 +93,7 @@ struct GridBwdArgs {
   const void* table_rad;
   const float* dfeat_geo;
   const float* dfeat_rad;
+  bool pos_done;         // the decoder adjoint already added dL/dp through the weights
   float* g_pos;
   float* g_table_geo;
   float* g_table_rad;

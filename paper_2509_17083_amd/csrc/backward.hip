@@ -598,14 +598,35 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
           *reinterpret_cast<float2*>(a.dfeat_rad + (size_t)item * 2 * Sh::L + 2 * lev) = make_float2(dfr[2 * k], dfr[2 * k + 1]);
         }
       }
+      // dL/dx through the interpolation weights from the feature derivatives
+      // the forward saved: dL/dx_d = sum_(l,f) dL/df (d f / d x_d)
+      float dxv[3] = {0.f, 0.f, 0.f};
+      if (a.jac && valid) {
+#pragma unroll
+        for (int k = 0; k < Sh::L / 4; ++k) {
+          const float4* J4 = reinterpret_cast<const float4*>(a.jac + ((size_t)item * Sh::L + g + 4 * k) * 12);
+          const float4 j0 = J4[0], j1 = J4[1], j2 = J4[2];
+          const float Jg[6] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y};
+          const float Jr[6] = {j1.z, j1.w, j2.x, j2.y, j2.z, j2.w};
+#pragma unroll
+          for (int d = 0; d < 3; ++d)
+            dxv[d] += (dxg[2 * k] * Jg[d] + dxg[2 * k + 1] * Jg[3 + d]) +
+                      (dfr[2 * k] * Jr[d] + dfr[2 * k + 1] * Jr[3 + d]);
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
         dp_dir[k] += __shfl_xor(dp_dir[k], 16, 64);
         dp_dir[k] += __shfl_xor(dp_dir[k], 32, 64);
+        dxv[k] += __shfl_xor(dxv[k], 16, 64);
+        dxv[k] += __shfl_xor(dxv[k], 32, 64);
       }
-      if (valid && g == 0 && a.g_pos)
+      if (valid && g == 0 && a.g_pos) {
+        float dpw[3] = {0.f, 0.f, 0.f};
+        if (a.jac) contract_vjp(a.grid, pxf, pyf, pzf, dxv, dpw);
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k];
+        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k] + dpw[k];
+      }
     } else if (valid) {
       // background points: feature gradients handed to the background grid adjoint
 #pragma unroll
@@ -727,6 +748,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const bool single = a.grid.single != 0;
   const bool do_geo = a.g_table_geo && !single;
+  const bool pos_done = a.pos_done;   // dL/dp through the weights added by the decoder adjoint
   double x[3];
   contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
   float dxv[3] = {0.f, 0.f, 0.f};
@@ -758,8 +780,8 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
                      cz = (uint32_t)ci[2] + ((c >> 2) & 1);
       rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
       rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-      vg[c] = valid && !single ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
-      vr[c] = valid ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
+      vg[c] = valid && !single && !pos_done ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
+      vr[c] = valid && !pos_done ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
     }
     float sg[16], sr[16];
 #pragma unroll
@@ -788,7 +810,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, rr, sr, st);
     }
   }
-  if (valid && a.g_pos) {
+  if (valid && a.g_pos && !pos_done) {
     float dp[3];
     contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
 #pragma unroll
@@ -935,6 +957,7 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.table_rad = a.table_rad;
     gb.dfeat_geo = a.dfeat_geo;
     gb.dfeat_rad = a.dfeat_rad;
+    gb.pos_done = a.jac != nullptr;
     gb.g_pos = a.g_pos;
     gb.g_table_geo = a.g_table_geo;
     gb.g_table_rad = a.g_table_rad;

@@ -247,11 +247,16 @@ __device__ __forceinline__ float2 load_entry(const uint8_t* t, size_t i) {
 
 // Gather this lane's levels from both tables at contracted position x.
 // fg / fr: lane features (level g + 4k, feature f) at index 2k + f.
+//
+// jac (nullable): this point's [L][12] row of spatial feature derivatives,
+// written for the lane's levels: d f / d x = sum_c table[c] d w_c / d x with
+// d w_c / d x_d = N_l * (+-1) * (product of the other two 1D weights); the
+// geometry half repeats the radiance half when GEO is false.
 template <int L, bool GEO, class TT>
 __device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], int g,
                                             const TT* __restrict__ tg, const TT* __restrict__ tr,
                                             float (&fg)[L / 2], float (&fr)[L / 2],
-                                            uint32_t* dbg_geo, uint32_t* dbg_rad) {
+                                            uint32_t* dbg_geo, uint32_t* dbg_rad, float* jac = nullptr) {
   const uint32_t Tg = gp.mask_geo + 1u, Tr = gp.mask_rad + 1u;
 #pragma unroll
   for (int k = 0; k < L / 4; ++k) {
@@ -292,6 +297,38 @@ __device__ __forceinline__ void gather_lane(const GridP& gp, const double x[3], 
         b0 = fmaf(wc[c], vg[c].x, b0);
         b1 = fmaf(wc[c], vg[c].y, b1);
       }
+    }
+    // (8-bit tables are a render-only format: no derivatives for them)
+    if (!std::is_same<TT, uint8_t>::value && jac) {
+      float jr[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, jg[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const float fres = (float)res;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const float wx = (c & 1) ? w[0] : 1.f - w[0];
+        const float wy = ((c >> 1) & 1) ? w[1] : 1.f - w[1];
+        const float wz = ((c >> 2) & 1) ? w[2] : 1.f - w[2];
+        const float dw[3] = {fres * ((c & 1) ? 1.f : -1.f) * (wy * wz),
+                             fres * (((c >> 1) & 1) ? 1.f : -1.f) * (wx * wz),
+                             fres * (((c >> 2) & 1) ? 1.f : -1.f) * (wx * wy)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          jr[d] = fmaf(vr[c].x, dw[d], jr[d]);
+          jr[3 + d] = fmaf(vr[c].y, dw[d], jr[3 + d]);
+          if (GEO) {
+            jg[d] = fmaf(vg[c].x, dw[d], jg[d]);
+            jg[3 + d] = fmaf(vg[c].y, dw[d], jg[3 + d]);
+          }
+        }
+      }
+      float4* o = reinterpret_cast<float4*>(jac + (size_t)lev * 12);
+      if (GEO) {
+        o[0] = make_float4(jg[0], jg[1], jg[2], jg[3]);
+        o[1] = make_float4(jg[4], jg[5], jr[0], jr[1]);
+      } else {
+        o[0] = make_float4(jr[0], jr[1], jr[2], jr[3]);
+        o[1] = make_float4(jr[4], jr[5], jr[0], jr[1]);
+      }
+      o[2] = make_float4(jr[2], jr[3], jr[4], jr[5]);
     }
     if constexpr (std::is_same<TT, uint8_t>::value) {
       const float2 qr = *reinterpret_cast<const float2*>(gp.qp_rad + 2 * lev);

@@ -29,6 +29,7 @@ struct QueryArgs {
   float* feat_geo;
   float* feat_rad;
   uint32_t* dbg;
+  float* jac;                 // [n][L][12] feature derivatives d f / d x, or NULL
 };
 
 struct BgArgs {

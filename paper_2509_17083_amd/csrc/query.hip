@@ -85,9 +85,10 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       dg = a.dbg + (size_t)slot * 2 * Sh::L * 8;
       dr = dg + Sh::L * 8;
     }
+    float* jac = a.jac && valid ? a.jac + (size_t)slot * Sh::L * 12 : nullptr;
     if (a.grid.single) {
       // one field feeds both decoders: gather it once
-      gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, table_rad, fg, fr, nullptr, dr);
+      gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, table_rad, fg, fr, nullptr, dr, jac);
 #pragma unroll
       for (int s = 0; s < Sh::FPL; ++s) fg[s] = fr[s];
       if (dg) {
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
           for (int c = 0; c < 8; ++c) dg[(g + 4 * k) * 8 + c] = dr[(g + 4 * k) * 8 + c];
       }
     } else {
-      gather_lane<Sh::L, true, TT>(a.grid, x, g, table_geo, table_rad, fg, fr, dg, dr);
+      gather_lane<Sh::L, true, TT>(a.grid, x, g, table_geo, table_rad, fg, fr, dg, dr, jac);
     }
     if (a.feat_geo && valid) {
 #pragma unroll

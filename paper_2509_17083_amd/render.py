@@ -226,11 +226,12 @@ def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool
     if mode == TRAIN:
         q["feat_geo"] = torch.empty(max(n, 1), 2 * L, device=dev)
         q["feat_rad"] = torch.empty(max(n, 1), 2 * L, device=dev)
+        q["feat_jac"] = torch.empty(max(n, 1), L, 12, device=dev)   # d(features)/dx for the backward
     if debug_index:
         q["dbg_index"] = torch.empty(max(n, 1), 2, L, 8, dtype=torch.int32, device=dev)
     out = A.hyrf_query_out(*[q[k].data_ptr() if k in q else None for k in
                              ("vis_count", "vis_idx", "opacity", "scale", "quat", "rgb", "feat_geo",
-                              "feat_rad", "dbg_index")])
+                              "feat_rad", "dbg_index", "feat_jac")])
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
     nb = lib.hyrf_query_workspace_bytes(n)
     w = ws.get("query", nb)

@@ -137,8 +137,12 @@ def test_staged_backward_equals_one_call():
     g3 = P.render_backward(ds, cams, st, dL, overlap=True)               # two branches, two streams
     import dataclasses
     g4 = P.render_backward(ds, cams, dataclasses.replace(st, bg_feat=None), dL)  # background features gathered again
+    from paper_2509_17083_amd import _abi as A
+    qo = A.hyrf_query_out.from_buffer_copy(st.c["qout"])
+    qo.feat_jac = None                                                    # dL/dp with tables gathered again
+    g5 = P.render_backward(ds, cams, dataclasses.replace(st, c=dict(st.c, qout=qo)), dL)
     torch.cuda.synchronize()
     for k, v in g1.items():
         if v is not None:
-            for g in (g2, g3, g4):
+            for g in (g2, g3, g4, g5):
                 assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
