@@ -220,19 +220,19 @@ def main():
         return
     # headline: the adjoint's Gaussian and background branches on two streams
     ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
-    bwd_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage0", "bwd_stage1"),
-                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_gauss_end"),
-                ("bwd_bg_decoders", "bwd_stage3", "bwd_stage4"), ("bwd_bg_tables", "bwd_stage4", "bwd_bg_end"),
-                ("bwd_dw", "bwd_stage5", "bwd_stage6"))
+    bwd_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage1", "bwd_stage2"),
+                ("bwd_decoders", "bwd_stage2", "bwd_stage3"), ("bwd_tables", "bwd_stage3", "bwd_gauss_end"),
+                ("bwd_bg_decoders", "bwd_stage4", "bwd_stage5"), ("bwd_bg_tables", "bwd_stage5", "bwd_bg_end"),
+                ("bwd_dw", "bwd_stage6", "bwd_stage7"))
     st_train = stages(ev_t, fwd_keys + bwd_keys)
     print(f"[bench] train step {ms_train:.3f} ms; stages (branches overlapped) {st_train}; loss {float(loss):.5f}; "
           f"entries {st.n_entries}", file=sys.stderr, flush=True)
     # the same step with every stage alone on one stream: per-kernel times
     ms_train_serial, ev_s, _ = timed(lambda ev: train_step(ev, overlap=False), args.steps)
-    ser_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage0", "bwd_stage1"),
-                ("bwd_decoders", "bwd_stage1", "bwd_stage2"), ("bwd_tables", "bwd_stage2", "bwd_stage3"),
-                ("bwd_bg_decoders", "bwd_stage3", "bwd_stage4"), ("bwd_bg_tables", "bwd_stage4", "bwd_stage5"),
-                ("bwd_dw", "bwd_stage5", "bwd_stage6"))
+    ser_keys = (("backward", "bwd0", "bwd1"), ("bwd_weights", "bwd_stage0", "bwd_stage1"),
+                ("bwd_splats", "bwd_stage1", "bwd_stage2"), ("bwd_decoders", "bwd_stage2", "bwd_stage3"),
+                ("bwd_tables", "bwd_stage3", "bwd_stage4"), ("bwd_bg_decoders", "bwd_stage4", "bwd_stage5"),
+                ("bwd_bg_tables", "bwd_stage5", "bwd_stage6"), ("bwd_dw", "bwd_stage6", "bwd_stage7"))
     st_serial = stages(ev_s, fwd_keys + ser_keys)
     print(f"[bench] train step, stages serial {ms_train_serial:.3f} ms; stages {st_serial}", file=sys.stderr,
           flush=True)
@@ -313,7 +313,7 @@ def main():
 
     # Roofline of the dominant kernel of the train step: the background
     # points' radiance-table adjoint (k_bg_grid_bwd, alone in backward stage
-    # 4 of the serial run).  Algorithmic bytes per background pixel: its feature gradient read
+    # 5 of the serial run).  Algorithmic bytes per background pixel: its feature gradient read
     # (2L floats) + for each of L levels x 8 corners one read-modify-write of
     # the 2-float table row (16 B).
     n_bg = V * H * W

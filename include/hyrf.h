@@ -258,21 +258,24 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
                                  const hyrf_grads* grads, void* ws, size_t ws_bytes,
                                  void* stream);
 
-/* The same adjoint split into six stages, for callers that overlap or time
+/* The same adjoint split into seven stages, for callers that overlap or time
  * them.  Every stage takes the same arguments and workspace; each reads what
  * the stages it depends on left in the workspace:
- *   0  blending and projection adjoints (explicit-parameter gradients,
- *      densification statistics); permutes the decoder weights
- *   1  decoder adjoints of the Gaussians                          (after 0)
- *   2  hash-table adjoint of the Gaussians: table gradients, dL/dp through
- *      the interpolation weights and the contraction               (after 1)
- *   3  colour-decoder adjoint of the background points             (after 0)
- *   4  radiance-table adjoint of the background points             (after 3)
- *   5  decoder weight gradients from the partials of 1 and 3   (after 1, 3)
- * The Gaussian branch (1, 2) and the background branch (3, 4) touch disjoint
- * workspace regions and meet only in atomic additions to the radiance-table
- * gradient, so they may run concurrently on two streams (the caller orders
- * them with events).  hyrf_render_backward == stages 0..5 on one stream. */
+ *   0  decoder weights permuted into the operand order of the adjoint
+ *   1  blending and projection adjoints (explicit-parameter gradients,
+ *      densification statistics)
+ *   2  decoder adjoints of the Gaussians; dL/dp through the view direction
+ *      and, with saved feature derivatives, through the interpolation
+ *      weights                                                    (after 0, 1)
+ *   3  hash-table adjoint of the Gaussians                         (after 2)
+ *   4  colour-decoder adjoint of the background points             (after 0)
+ *   5  radiance-table adjoint of the background points             (after 4)
+ *   6  decoder weight gradients from the partials of 2 and 4   (after 2, 4)
+ * The Gaussian branch (1, 2, 3) and the background branch (4, 5) touch
+ * disjoint workspace regions and meet only in atomic additions to the
+ * radiance-table gradient, so they may run concurrently on two streams (the
+ * caller orders them with events).  hyrf_render_backward == stages 0..6 on
+ * one stream. */
 hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields, const hyrf_gaussians* g,
                                        const hyrf_camera* cams, int32_t n_views,
                                        const hyrf_fwd_state* saved, const float* dL_drgb,

@@ -528,7 +528,7 @@ hyrf_status hyrf_render_backward_stage(int32_t stage, const hyrf_fields* fields,
                                        const hyrf_camera* cams, int32_t n_views, const hyrf_fwd_state* saved,
                                        const float* dL_drgb, const hyrf_grads* grads, void* ws, size_t ws_bytes,
                                        void* stream) {
-  REQ(stage >= 0 && stage <= 5, "stage = %d outside [0, 5]", stage);
+  REQ(stage >= 0 && stage <= 6, "stage = %d outside [0, 6]", stage);
   return backward_impl(1 << stage, fields, g, cams, n_views, saved, dL_drgb, grads, ws, ws_bytes, stream);
 }
 

@@ -107,18 +107,19 @@ struct BgGridArgs {
   float* g_table_rad;
 };
 
-// Stages of the adjoint.  SPLATS first; then two independent branches --
-// Gaussians (DECODERS, then TABLES) and background points (BG_DECODERS, then
+// Stages of the adjoint.  WEIGHTS first; then two independent branches --
+// Gaussians (SPLATS, DECODERS, TABLES) and background points (BG_DECODERS,
 // BG_TABLES) -- which may run concurrently on two streams; DW after both
 // decoder stages.
 enum : int {
-  BWD_STAGE_SPLATS = 1,        // blending + projection adjoints, decoder weights permuted
-  BWD_STAGE_DECODERS = 2,      // decoder adjoints of the Gaussians -> dW partials, feature grads
-  BWD_STAGE_TABLES = 4,        // Gaussians' hash-table adjoint -> table grads, position grads
-  BWD_STAGE_BG_DECODERS = 8,   // colour-decoder adjoint of the background points
-  BWD_STAGE_BG_TABLES = 16,    // background points' radiance-table adjoint
-  BWD_STAGE_DW = 32,           // dW partials -> decoder weight gradients
-  BWD_STAGE_ALL = 63
+  BWD_STAGE_WEIGHTS = 1,       // decoder weights permuted into the MFMA operand order
+  BWD_STAGE_SPLATS = 2,        // blending + projection adjoints
+  BWD_STAGE_DECODERS = 4,      // decoder adjoints of the Gaussians -> dW partials, feature grads
+  BWD_STAGE_TABLES = 8,        // Gaussians' hash-table adjoint -> table grads
+  BWD_STAGE_BG_DECODERS = 16,  // colour-decoder adjoint of the background points
+  BWD_STAGE_BG_TABLES = 32,    // background points' radiance-table adjoint
+  BWD_STAGE_DW = 64,           // dW partials -> decoder weight gradients
+  BWD_STAGE_ALL = 127
 };
 
 struct BwdLaunch {

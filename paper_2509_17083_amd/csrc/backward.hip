@@ -926,14 +926,14 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
   FieldBwdArgs a = L.field;
   a.wf_geo = L.wf_geo; a.wf_col = L.wf_col; a.wb_geo = L.wb_geo; a.wb_col = L.wb_col;
   a.n_w = Sh::N_GEO + Sh::N_COL;
+  if (L.stages & BWD_STAGE_WEIGHTS)
+    k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
   if (L.stages & BWD_STAGE_SPLATS) {
-    // per-splat gradient records, then the projection adjoint; the decoder
-    // weights are permuted here so that both decoder stages can follow
+    // per-splat gradient records, then the projection adjoint
     k_zero_f32<<<nblk(L.n_gs), 256, 0, st>>>(L.comp.gs, L.n_gs);
     dim3 grid(L.comp.tiles_x, L.comp.tiles_y, L.V);
     k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
     k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
-    k_prep_weights<Sh, BF><<<64, 256, 0, st>>>(L.w_geo, L.w_col, L.wf_geo, L.wf_col, L.wb_geo, L.wb_col);
   }
   if (L.stages & BWD_STAGE_DECODERS) k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
   if ((L.stages & BWD_STAGE_BG_DECODERS) && L.with_bg) {

@@ -397,13 +397,14 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
                                              C.byref(cg), _p(w), w.numel(), _stream()))
             return grads
         main = torch.cuda.current_stream()
-        for k in range(6):
+        for k in range(7):
             _mark(events, f"bwd_stage{k}")
             stage(k, main)
-        _mark(events, "bwd_stage6")
+        _mark(events, "bwd_stage7")
         return grads
-    # two streams: the Gaussian branch (stages 1, 2) on the caller's stream,
-    # the background branch (stages 3, 4) on a side stream, joined before 5
+    # two streams: after the weight permutation (0), the background branch
+    # (stages 4, 5) runs on a side stream while the Gaussian branch (1, 2, 3)
+    # runs on the caller's stream; they join before the weight gradients (6)
     main = torch.cuda.current_stream()
     side = ws.side_stream()
     _mark(events, "bwd_stage0")
@@ -411,22 +412,24 @@ def render_backward(scene: DeviceScene, cams, st: ForwardState, dL_drgb: torch.T
     e0 = torch.cuda.Event()
     e0.record(main)
     side.wait_event(e0)
+    _mark(events, "bwd_stage4", side)
+    stage(4, side)
+    _mark(events, "bwd_stage5", side)
+    stage(5, side)
+    _mark(events, "bwd_bg_end", side)
+    e1 = torch.cuda.Event()
+    e1.record(side)
     _mark(events, "bwd_stage1")
     stage(1, main)
     _mark(events, "bwd_stage2")
     stage(2, main)
+    _mark(events, "bwd_stage3")
+    stage(3, main)
     _mark(events, "bwd_gauss_end")
-    _mark(events, "bwd_stage3", side)
-    stage(3, side)
-    _mark(events, "bwd_stage4", side)
-    stage(4, side)
-    _mark(events, "bwd_bg_end", side)
-    e1 = torch.cuda.Event()
-    e1.record(side)
     main.wait_event(e1)
-    _mark(events, "bwd_stage5")
-    stage(5, main)
     _mark(events, "bwd_stage6")
+    stage(6, main)
+    _mark(events, "bwd_stage7")
     return grads
 
 
