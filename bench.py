@@ -210,10 +210,12 @@ def main():
         return (time.perf_counter() - t0) * 1e3 / steps, ev, out
 
     def stages(ev, keys):
-        return {k: float(np.mean([_ms(a, b) for a, b in zip(ev[k0], ev[k1])])) for k, k0, k1 in keys}
+        return {k: float(np.mean([_ms(a, b) for a, b in zip(ev[k0], ev[k1])])) for k, k0, k1 in keys
+                if k0 in ev and k1 in ev}
 
     fwd_keys = (("query", "query0", "query1"), ("project", "query1", "project1"),
-                ("bin_sort", "bin0", "bin1"), ("composite", "bin1", "composite1"))
+                ("bin_sort", "bin0", "bin1"), ("composite", "bin1", "composite1"),
+                ("background_side_stream", "bg0", "bg1"))
     if args.render_only:
         ms_render, ev_r, st_r = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=ev), args.steps)
         print(json.dumps({"render_ms": round(ms_render, 4), "stages": stages(ev_r, fwd_keys)}), flush=True)

@@ -246,6 +246,22 @@ hyrf_status hyrf_composite(const hyrf_splats* splats, const uint32_t* vals,
                            float* out_rgb, float* out_T, int32_t* out_last, float* out_bg,
                            float* out_bg_feat, void* ws, size_t ws_bytes, void* stream);
 
+/* The train-mode background on its own (Sec. 3.3 Eqs. 10-11): c_s of every
+ * pixel of every view, out_bg [V][3][H][W], and (nullable) the sphere points'
+ * radiance features out_bg_feat [V*H*W][2L] kept for the backward.  It
+ * depends on the cameras and fields only, so a caller may run it on a second
+ * stream while the Gaussians are queried, projected, sorted and blended
+ * (hyrf_composite with fields = NULL), then add it with
+ * hyrf_blend_background.  The result equals hyrf_composite with fields in
+ * TRAIN mode. */
+hyrf_status hyrf_background(const hyrf_fields* fields, const hyrf_camera* cams, int32_t n_views, float* out_bg,
+                            float* out_bg_feat, void* stream);
+
+/* rgb[v][c][p] += T[v][p] * bg[v][c][p] over [V][3][H][W] (Eq. 10: the
+ * background seen through the final transmittance). */
+hyrf_status hyrf_blend_background(const float* bg, const float* T, float* rgb, int32_t n_views, int32_t width,
+                                  int32_t height, void* stream);
+
 /* Adjoint of the whole step: given dL/dC [V][3][H][W], accumulates (+=) the
  * gradients of every explicit parameter, both hash tables (background uses
  * included) and both decoders' weights.  Predicates (pre-cull, alpha

@@ -78,6 +78,8 @@ EXPORTS = {
                                 C.c_int64, P, P, P, P, C.c_size_t, P]),
     "hyrf_composite": (C.c_int, [C.POINTER(hyrf_splats), P, P, C.POINTER(hyrf_camera), C.c_int32,
                                  C.POINTER(hyrf_fields), C.c_int32, P, P, P, P, P, P, C.c_size_t, P]),
+    "hyrf_background": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_camera), C.c_int32, P, P, P]),
+    "hyrf_blend_background": (C.c_int, [P, P, P, C.c_int32, C.c_int32, C.c_int32, P]),
     "hyrf_render_backward": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians), C.POINTER(hyrf_camera),
                                        C.c_int32, C.POINTER(hyrf_fwd_state), P, C.POINTER(hyrf_grads), P,
                                        C.c_size_t, P]),

@@ -340,6 +340,36 @@ hyrf_status hyrf_composite(const hyrf_splats* sp, const uint32_t* vals, const ui
   return check_launch();
 }
 
+hyrf_status hyrf_background(const hyrf_fields* fields, const hyrf_camera* cams, int32_t n_views, float* out_bg,
+                            float* out_bg_feat, void* stream) {
+  hyrf_status s;
+  if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
+  if ((s = check_fields(fields)) != HYRF_OK) return s;
+  REQ(out_bg, "out_bg is NULL");
+  const int W = cams[0].width, H = cams[0].height;
+  BgArgs b{};
+  b.grid = make_grid(fields);
+  b.cams = make_cams(cams, n_views);
+  b.table_rad = fields->table_rad;
+  b.w_col = fields->mlp_col;
+  b.W = W;
+  b.H = H;
+  b.bg_save = out_bg;
+  b.feat_save = out_bg_feat;
+  launch_bg(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype, fields->mlp_dtype == HYRF_BF16,
+            b, n_views * W * H, (hipStream_t)stream);
+  return check_launch();
+}
+
+hyrf_status hyrf_blend_background(const float* bg, const float* T, float* rgb, int32_t n_views, int32_t width,
+                                  int32_t height, void* stream) {
+  REQ(bg && T && rgb, "bg / T / rgb is NULL");
+  REQ(n_views >= 1 && width > 0 && height > 0, "sizes must be positive");
+  REQ((int64_t)n_views * 3 * width * height < ((int64_t)1 << 40), "image too large");
+  launch_blend_bg(bg, T, rgb, n_views, width * height, (hipStream_t)stream);
+  return check_launch();
+}
+
 size_t hyrf_l1_workspace_bytes(int64_t n) { return l1_ws_elems(n) * sizeof(float); }
 
 hyrf_status hyrf_l1_loss(const float* img, const float* target, int64_t n, float* loss, float* grad,

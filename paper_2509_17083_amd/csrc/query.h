@@ -40,8 +40,8 @@ struct BgArgs {
   int W, H;
   const uint32_t* list;        // pixel ids v*H*W + y*W + x, or NULL = every pixel
   const uint32_t* list_count;  // device count of `list`, or NULL
-  const float* T;              // [V][H][W] final transmittance
-  float* out_rgb;              // [V][3][H][W]: C_fg in, C_fg + T c_s out
+  const float* T;              // [V][H][W] final transmittance (with out_rgb)
+  float* out_rgb;              // [V][3][H][W]: C_fg in, C_fg + T c_s out; or NULL (c_s only)
   float* bg_save;              // [V][3][H][W] c_s, or NULL
   float* feat_save;            // [V*H*W][2L] radiance features of the sphere points, or NULL
 };
@@ -51,6 +51,8 @@ bool shape_supported(int L, int hid, int nh);
 bool precision_supported(int L, int hid, int nh, int tdt, bool bf);
 void launch_query(int L, int hid, int nh, int tdt, bool bf, const QueryArgs& a, int n_cap, hipStream_t st);
 void launch_bg(int L, int hid, int nh, int tdt, bool bf, const BgArgs& a, int n_cap, hipStream_t st);
+// rgb[v][c][p] += T[v][p] * bg[v][c][p]
+void launch_blend_bg(const float* bg, const float* T, float* rgb, int V, int HW, hipStream_t st);
 void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
                  uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st);
 

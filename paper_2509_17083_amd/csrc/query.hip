@@ -199,12 +199,12 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
             make_float2(fr[2 * k], fr[2 * k + 1]);
     }
     if (g == 0 && valid) {
-      const float T = a.T[pix];
+      const float T = a.out_rgb ? a.T[pix] : 0.f;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         const float cs = sigmoidf_(o[c]);
         const size_t at = ((size_t)v * 3 + c) * HW + rem;
-        a.out_rgb[at] = fmaf(T, cs, a.out_rgb[at]);
+        if (a.out_rgb) a.out_rgb[at] = fmaf(T, cs, a.out_rgb[at]);
         if (a.bg_save) a.bg_save[at] = cs;
       }
     }
@@ -271,6 +271,20 @@ void launch_bg(int L, int hid, int nh, int tdt, bool bf, const BgArgs& a, int n_
 bool precision_supported(int L, int hid, int nh, int tdt, bool bf) {
   if ((tdt == HYRF_F32 || tdt == HYRF_U8) && !bf) return shape_supported(L, hid, nh);
   return L == 16 && hid == 64 && nh == 2;
+}
+
+__global__ __launch_bounds__(256) void k_blend_bg(const float* __restrict__ bg, const float* __restrict__ T,
+                                                  float* __restrict__ rgb, int HW, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;   // over V * 3 * HW
+  if (i >= n) return;
+  const int64_t v = i / (3 * (int64_t)HW);
+  const int64_t p = i - (i / HW) * HW;
+  rgb[i] = fmaf(T[v * HW + p], bg[i], rgb[i]);
+}
+
+void launch_blend_bg(const float* bg, const float* T, float* rgb, int V, int HW, hipStream_t st) {
+  const int64_t n = (int64_t)V * 3 * HW;
+  k_blend_bg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(bg, T, rgb, HW, n);
 }
 
 void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,

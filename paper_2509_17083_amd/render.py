@@ -303,13 +303,34 @@ def _mark(events, name, stream=None):
 
 
 def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False, want_keys: bool = False,
-           ws: Optional[Workspace] = None, events: Optional[dict] = None) -> ForwardState:
+           ws: Optional[Workspace] = None, events: Optional[dict] = None, overlap: bool = False) -> ForwardState:
     """The forward render step: query -> project -> bin/sort -> composite
     (+ background).  One host read (the tile-entry count).  `events`, if
-    given, collects torch.cuda.Event pairs (on the current stream, where
-    every kernel is launched) around each ABI call."""
+    given, collects torch.cuda.Event pairs around each ABI call.  In TRAIN
+    mode with `overlap`, the background of every pixel (which needs only the
+    cameras and the fields) runs on a second stream, concurrent with the
+    Gaussian path, and is blended in at the end (off by default: both paths
+    are gather-bound, so at full size they mostly share the memory system
+    rather than overlap)."""
+    lib = A.load()
     ws = ws or Workspace()
     V, W, H = len(cams), cams[0].width, cams[0].height
+    split_bg = mode == TRAIN and overlap
+    if split_bg:
+        bg = torch.empty(V, 3, H, W, device="cuda")
+        bg_feat = torch.empty(V * H * W, 2 * scene.levels, device="cuda")
+        main = torch.cuda.current_stream()
+        side = ws.side_stream()
+        e_start = torch.cuda.Event()
+        e_start.record(main)
+        side.wait_event(e_start)
+        f_bg, cc_bg = scene.c_fields(), c_cameras(cams)
+        _mark(events, "bg0", side)
+        A.check("hyrf_background", lib.hyrf_background(C.byref(f_bg), cc_bg, V, _p(bg), _p(bg_feat),
+                                                       C.c_void_p(side.cuda_stream)))
+        _mark(events, "bg1", side)
+        e_bg = torch.cuda.Event()
+        e_bg.record(side)
     _mark(events, "query0")
     q, qout = query_fields(scene, cams, mode, debug_index, ws)
     _mark(events, "query1")
@@ -319,7 +340,12 @@ def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = Fal
     _mark(events, "bin0")
     keys, vals, ranges = bin_sort(cams, spc, max(scene.n, 1), n_entries, want_keys, ws)
     _mark(events, "bin1")
-    img, T, last, bg, bg_feat = composite(scene, cams, spc, vals, ranges, mode, ws)
+    if split_bg:
+        img, T, last, _, _ = composite(None, cams, spc, vals, ranges, mode, ws)
+        main.wait_event(e_bg)
+        A.check("hyrf_blend_background", lib.hyrf_blend_background(_p(bg), _p(T), _p(img), V, W, H, _stream()))
+    else:
+        img, T, last, bg, bg_feat = composite(scene, cams, spc, vals, ranges, mode, ws)
     _mark(events, "composite1")
     return ForwardState(mode=mode, V=V, W=W, H=H, n_entries=n_entries, query=q, splats=sp, vals=vals,
                         keys=keys, ranges=ranges, image=img, T=T, last=last, bg=bg, bg_feat=bg_feat,

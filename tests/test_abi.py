@@ -140,3 +140,14 @@ def test_l1_dssim_rejects_bad_arguments():
         args = list(good)
         args[i] = bad
         assert lib.hyrf_l1_dssim_loss(*args) == A.HYRF_ERR_INVALID_ARGUMENT, (i, bad)
+
+
+def test_background_entry_points_reject_bad_arguments():
+    A, lib = _lib()
+    f = _fields(A)
+    assert lib.hyrf_background(C.byref(f), _cam(A), 1, None, None, None) == A.HYRF_ERR_INVALID_ARGUMENT
+    assert lib.hyrf_background(None, _cam(A), 1, C.c_void_p(0x100), None, None) == A.HYRF_ERR_INVALID_ARGUMENT
+    assert lib.hyrf_blend_background(None, C.c_void_p(0x100), C.c_void_p(0x200), 1, 4, 4, None) == \
+        A.HYRF_ERR_INVALID_ARGUMENT
+    assert lib.hyrf_blend_background(C.c_void_p(0x1), C.c_void_p(0x100), C.c_void_p(0x200), 1, 0, 4, None) == \
+        A.HYRF_ERR_INVALID_ARGUMENT

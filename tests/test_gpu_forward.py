@@ -187,6 +187,19 @@ def test_render_empty_scene_is_background():
         assert res["ok"], res
 
 
+def test_train_background_on_a_second_stream_equals_one_stream():
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    ds = device_scene(scene)
+    a = P.render(ds, cams, P.TRAIN, overlap=True)
+    b = P.render(ds, cams, P.TRAIN, overlap=False)
+    torch.cuda.synchronize()
+    assert torch.equal(a.bg, b.bg) and torch.equal(a.bg_feat, b.bg_feat) and torch.equal(a.T, b.T)
+    # c_fg + T c_s: one fused multiply-add in both
+    assert torch.equal(a.image, b.image)
+
+
 def test_forward_is_deterministic():
     P = _P()
     cfg, scene, cams = make("tiny", table_init=1.0)
