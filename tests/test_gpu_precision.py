@@ -87,3 +87,60 @@ def test_variant_gradient_error_against_fp64_oracle():
     for k in e32:
         assert e32[k] < 1e-3, (k, e32[k])
         assert ev[k] < 0.1, (k, ev[k])
+
+
+@pytest.mark.timeout(900)
+def test_fp32_and_variant_on_the_1080p_crop():
+    """The full-size scene (1M Gaussians, tables 2^21 / 2^20, 2x64 decoders)
+    seen through the 256 x 256 window [832, 1088) x [412, 668) of the 1080p
+    camera: FP32 and variant images and gradients of L = sum(w * C) against the
+    FP64 oracle (one forward + autograd pass, about a minute of CPU)."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _hyrf_testutil import compare_image, knife_mask
+    P = _P()
+    cfg = hi.CONFIGS["c1m"]
+    scene = hi.make_scene(cfg)
+    cam = hi.crop_camera(hi.make_cameras(cfg)[0], 832, 412, 256, 256)
+    H = W = 256
+    print("oracle on the crop ...", flush=True)
+    params, fields = O.from_scene(scene, requires_grad=True)
+    r = O.render_view(params, fields, cam, O.TRAIN, return_stats=True)
+    knife = knife_mask(r, O.TRAIN).reshape(H, W)
+    w = torch.from_numpy(hi.make_target_image((3, H, W), seed=19) - 0.5).double() * (~knife).double()[None]
+    img_ref = r["rgb"].T.reshape(3, H, W)
+    L = torch.sum(img_ref * w)
+    names = ["pos", "opac_e", "col_e", "table_geo", "table_rad"]
+    leaves = [params.pos, params.opac_e, params.col_e, fields.table_geo, fields.table_rad]
+    gs = torch.autograd.grad(L, leaves + list(fields.mlp_geo) + list(fields.mlp_col))
+    ref = dict(zip(names, gs[:5]))
+    ref["mlp_geo"] = torch.cat([g.reshape(-1) for g in gs[5:5 + len(fields.mlp_geo)]])
+    ref["mlp_col"] = torch.cat([g.reshape(-1) for g in gs[5 + len(fields.mlp_geo):]])
+    ref_img = img_ref.detach().numpy()
+    print("oracle done", flush=True)
+    dL = torch.from_numpy(w.float().numpy()).cuda()[None].contiguous()
+    tgt = hi.make_target_image((3, H, W), seed=2001)
+    ds = P.DeviceScene.from_host(scene)
+    res = {}
+    for name, d in (("fp32", ds), ("f16+bf16", ds.with_precision(P.F16, P.BF16))):
+        st = P.render(d, [cam], P.TRAIN)
+        gr = P.render_backward(d, [cam], st, dL)
+        torch.cuda.synchronize()
+        img = st.image[0].cpu().numpy()
+        errs = {}
+        for k, rr in ref.items():
+            g = gr[k].detach().cpu().double()
+            g = g.T if k in ("pos", "col_e") else g
+            errs[k] = float((g - rr.reshape(g.shape)).norm() / rr.norm())
+        res[name] = dict(img=img, psnr_vs_fp64=psnr(img, ref_img), psnr_target=psnr(img, tgt), grad_rel=errs)
+        print(name, "PSNR vs FP64 %.2f dB" % res[name]["psnr_vs_fp64"], "gradient rel. L2",
+              {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    c = compare_image(res["fp32"]["img"], {"rgb": r["rgb"].detach(), "T": r["T"].detach(), "stats": r["stats"]},
+                      O.TRAIN, H, W)
+    assert c["ok"], c
+    assert all(e < 1e-3 for e in res["fp32"]["grad_rel"].values()), res["fp32"]["grad_rel"]
+    d = res["f16+bf16"]["psnr_target"] - res["fp32"]["psnr_target"]
+    print("variant: PSNR vs target minus FP32's: %.4f dB" % d, flush=True)
+    assert abs(d) <= 0.05
+    assert res["f16+bf16"]["psnr_vs_fp64"] > 40
+    assert all(e < 0.1 for e in res["f16+bf16"]["grad_rel"].values()), res["f16+bf16"]["grad_rel"]
