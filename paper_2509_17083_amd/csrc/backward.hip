@@ -428,6 +428,18 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   constexpr int ACC = B::ACC;
   __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
   __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
+  // the colour decoder's permuted weights (forward and adjoint operand
+  // orders; float32 or bfloat16 bytes) live in LDS for the whole persistent
+  // loop: every MFMA A operand is then an LDS read, not an L2 round trip
+  __shared__ __attribute__((aligned(16))) float s_wf_col[Sh::W_COL];
+  __shared__ __attribute__((aligned(16))) float s_wb_col[B::WB_COL];
+  {
+    const float4* src_f = reinterpret_cast<const float4*>(a.wf_col);
+    const float4* src_b = reinterpret_cast<const float4*>(a.wb_col);
+    for (int i = threadIdx.x; i < Sh::W_COL / 4; i += BWD_NT) reinterpret_cast<float4*>(s_wf_col)[i] = src_f[i];
+    for (int i = threadIdx.x; i < B::WB_COL / 4; i += BWD_NT) reinterpret_cast<float4*>(s_wb_col)[i] = src_b[i];
+    __syncthreads();
+  }
   const int lane = lane_id();
   const int j = lane & 15, g = lane >> 4;
   const int w = threadIdx.x / 64;
@@ -556,7 +568,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         x1c[s] = !valid ? 0.f : (s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f));
       float hc[Sh::NH][Sh::S_HID];
       v4f oc4;
-      D::template fwd<D::SC>(a.wf_col, x1c, hc, oc4, lane);
+      D::template fwd<D::SC>(s_wf_col, x1c, hc, oc4, lane);
       v4f dc = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         if constexpr (!RAY) {
@@ -573,7 +585,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         }
       }
       float dxc[D::SC];
-      D::template bwd<true, D::SC, ACC>(a.wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+      D::template bwd<true, D::SC, ACC>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
       for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
       if constexpr (!RAY) {
