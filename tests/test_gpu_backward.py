@@ -146,3 +146,53 @@ def test_staged_backward_equals_one_call():
         if v is not None:
             for g in (g2, g3, g4, g5):
                 assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
+
+
+def test_gradient_matches_central_differences_along_random_directions():
+    """Directional derivatives of L = sum(w * C) by central differences of the
+    FP64 oracle forward, along seeded random directions over the explicit
+    parameters and both tables, against the GPU gradient's projection."""
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    scene.scale_e += np.float32(1.0)
+    cam = cams[0]
+    H, W = cam.height, cam.width
+    w_img = hi.make_target_image((3, H, W), seed=31) - 0.5
+    _, w_masked, _ = _oracle_grads(scene, cam, w_img)   # knife-edge pixels weighted 0
+    ds = device_scene(scene)
+    st = P.render(ds, cams, P.TRAIN)
+    g = P.render_backward(ds, cams, st, torch.from_numpy(w_masked).cuda()[None])
+    torch.cuda.synchronize()
+    names = ["pos", "scale_e", "opac_e", "col_e", "table_geo", "table_rad"]
+    gpu = {k: g[k].detach().cpu().double().numpy() for k in names}
+    base = {k: getattr(scene, k).astype(np.float64) for k in names}
+    wt = torch.from_numpy(w_masked).double()
+    rng = np.random.default_rng(37)
+
+    def loss(shift):
+        import copy
+        sc = copy.deepcopy(scene)
+        for k in names:
+            setattr(sc, k, base[k] + shift[k])
+        params, fields = O.from_scene(sc)
+        with torch.no_grad():
+            r = O.render_view(params, fields, cam, O.TRAIN)
+        return float(torch.sum(r["rgb"].T.reshape(3, H, W) * wt))
+
+    # A step of 1e-7 keeps nearly every predicate (alpha threshold,
+    # termination, depth order, cull) on the side it takes at the float32
+    # parameters; a direction whose central differences at h and h/2
+    # disagree crosses one (the loss jumps there) and is reported, not used.
+    h = 1e-7
+    used = 0
+    for it in range(8):
+        v = {k: rng.normal(size=base[k].shape) * (0.05 if k.startswith("table") else 1.0) for k in names}
+        fd = (loss({k: h * v[k] for k in names}) - loss({k: -h * v[k] for k in names})) / (2 * h)
+        fd2 = (loss({k: 0.5 * h * v[k] for k in names}) - loss({k: -0.5 * h * v[k] for k in names})) / h
+        an = sum(float(np.sum(gpu[k] * v[k])) for k in names)
+        print("direction", it, "fd", fd, "fd(h/2)", fd2, "gpu", an, flush=True)
+        if abs(fd - fd2) > 1e-4 * max(1.0, abs(fd)):
+            continue
+        used += 1
+        assert abs(fd - an) <= 2e-3 * max(1.0, abs(fd)), (it, fd, an)
+    assert used >= 6

@@ -235,3 +235,37 @@ def test_spatial_order_is_a_permutation_and_render_is_unchanged():
     r = oracle_view(sc2, cams[0], O.TRAIN)
     res = compare_image(st.image[0].cpu().numpy(), r, O.TRAIN, 64, 64)
     assert res["ok"], res
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("mode", [O.TRAIN, O.RENDER])
+def test_full_size_1080p_sampled_pixels(mode):
+    """The benchmark's launch configuration -- 1M Gaussians, tables 2^21 /
+    2^20, 1920x1080, every tile -- against the oracle evaluated pixel by
+    pixel on 384 seeded pixels."""
+    P = _P()
+    cfg = hi.CONFIGS["c1m"]
+    scene = hi.make_scene(cfg)
+    cam = hi.make_cameras(cfg)[0]
+    ds = device_scene(scene)
+    st = P.render(ds, [cam], mode)
+    torch.cuda.synchronize()
+    img = st.image[0].cpu().numpy()
+    T_gpu = st.T[0].cpu().numpy()
+    _say("entries", st.n_entries)
+    rng = np.random.default_rng(23)
+    px = rng.integers(0, cam.width, 384)
+    py = rng.integers(0, cam.height, 384)
+    params, fields = O.from_scene(scene)
+    with torch.no_grad():
+        r = O.render_view(params, fields, cam, mode, pixels=torch.from_numpy(np.stack([px, py], 1)).long(),
+                          return_stats=True)
+    from _hyrf_testutil import knife_mask
+    knife = knife_mask(r, mode).numpy()
+    ref = r["rgb"].numpy()
+    got = img[:, py, px].T
+    diff = np.abs(got.astype(np.float64) - ref).max(axis=1)
+    _say("sampled max err", float(diff[~knife].max()), "knife", int(knife.sum()))
+    assert knife.mean() <= 0.05
+    assert float(diff[~knife].max()) <= 1e-5
+    assert float(np.abs(T_gpu[py, px] - r["T"].numpy())[~knife].max()) <= 1e-4
