@@ -322,11 +322,31 @@ def main():
     per_px = 2 * cfg.levels * 4 + cfg.levels * 8 * 16
     bg_ms = st_serial["bwd_bg_tables"]
     ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
+    # the scatter's real bound: float atomics.  Reference rate: torch's
+    # index_add_ of 64M values at random indices of a 256 MB buffer (one
+    # float atomic per value); the kernel issues L x 8 corners x 2 features
+    # float additions per pixel before its register / LDS reductions.
+    buf = torch.zeros(64 << 20, device="cuda")
+    idx = torch.randint(0, buf.numel(), (64 << 20,), device="cuda", generator=torch.Generator("cuda").manual_seed(5))
+    vals = torch.ones(idx.numel(), device="cuda")
+    buf.index_add_(0, idx, vals)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        buf.index_add_(0, idx, vals)
+    e1.record()
+    torch.cuda.synchronize()
+    atomic_rate = 3 * idx.numel() / (e0.elapsed_time(e1) * 1e-3)
+    del buf, idx, vals
+    adds = n_bg * cfg.levels * 8 * 2
+    atomics = {"float_adds_per_launch": adds, "adds_per_s": round(adds / (bg_ms * 1e-3) / 1e9, 1),
+               "random_atomics_per_s_measured": round(atomic_rate / 1e9, 1), "unit": "G/s",
+               "reference": "torch index_add_, 64M values at random indices of 64M floats"}
     roof = {"kernel": "k_bg_grid_bwd", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_bg_grid_bwd"),
             "algorithmic_bytes": n_bg * per_px,
             "bytes_per_pixel": per_px, "pixels": n_bg, "kernel_ms": round(bg_ms, 4),
-            "share_of_step": round(bg_ms / ms_train, 3)}
+            "share_of_step": round(bg_ms / ms_train, 3), "atomics": atomics}
     # the dominant forward kernel: the field query (gather-bound); bytes per
     # surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B
     # + explicit parameters read (56 B) + aggregated properties written (44 B)
