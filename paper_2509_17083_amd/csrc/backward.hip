@@ -97,7 +97,10 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
       float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbb = 0.f;
       if (contrib) {
         const float cb = s2[k].x;
-        T = T / (1.f - alpha);
+        // 1 - alpha >= 0.01: the hardware reciprocal (1 ulp) replaces two
+        // full divisions
+        const float inv1ma = __builtin_amdgcn_rcpf(1.f - alpha);
+        T = T * inv1ma;
         const float wgt = alpha * T;
         gr = wgt * g0;
         gg = wgt * g1;
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
         lc0 = q1.z; lc1 = q1.w; lc2 = cb;
         float dLda = ((q1.z - acc0) * g0 + (q1.w - acc1) * g1 + (cb - acc2) * g2) * T;
         la = alpha;
-        dLda += (-Tfin / (1.f - alpha)) * bgd;
+        dLda += (-Tfin * inv1ma) * bgd;
         if (og <= ALPHA_MAX) {
           go = G * dLda;
           const float dp = alpha * dLda;
