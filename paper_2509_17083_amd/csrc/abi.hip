@@ -15,7 +15,11 @@
 #include "project.h"
 #include "query.h"
 
-namespace { constexpr int POINTS_PER_ROUND_ABI = 128; }
+namespace {
+// Points one decoder-adjoint workgroup stages per round: 4 waves of 16
+// Gaussians, 8 waves of 16 background pixels.
+constexpr int64_t BWD_PPR_GAUSS = 64, BWD_PPR_BG = 128;
+}
 
 using namespace hyrf;
 
@@ -535,8 +539,8 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   L.wf_col = w.wf_col;
   L.wb_geo = w.wb_geo;
   L.wb_col = w.wb_col;
-  const int64_t rg = ((int64_t)g->n + POINTS_PER_ROUND_ABI - 1) / POINTS_PER_ROUND_ABI;
-  const int64_t rr = ((int64_t)n_views * W * H + POINTS_PER_ROUND_ABI - 1) / POINTS_PER_ROUND_ABI;
+  const int64_t rg = ((int64_t)g->n + BWD_PPR_GAUSS - 1) / BWD_PPR_GAUSS;
+  const int64_t rr = ((int64_t)n_views * W * H + BWD_PPR_BG - 1) / BWD_PPR_BG;
   L.blocks_g = (int)(rg < 1 ? 1 : (rg > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rg));
   L.blocks_r = (int)(rr < 1 ? 1 : (rr > BWD_MAX_BLOCKS ? BWD_MAX_BLOCKS : rr));
   L.with_bg = true;

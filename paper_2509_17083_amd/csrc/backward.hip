@@ -317,58 +317,58 @@ struct Dec {
     if constexpr (BF) mlp_forward_keep_bf16<Sh, S1>((const __bf16*)W, x, h, o, lane);
     else mlp_forward_keep<Sh, S1>((const float*)W, x, h, o, lane);
   }
-  template <bool COL, int S1, int ACC>
+  template <bool COL, int S1, int ACC, int NWV>
   static __device__ void bwd(const void* W, const float (&x)[S1], const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                              float (&dx)[S1], float* Xs, float* Ys, v4f (&acc)[ACC], int w, int lane) {
-    if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
-    else mlp_backward<Sh, COL, S1, ACC>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+    if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC, NWV>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+    else mlp_backward<Sh, COL, S1, ACC, NWV>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
   }
 };
 
 // Write the dW tiles of one layer (tile ids ID0 ..) owned by this wave.
-template <int ID0, int TO, int TI, int ACC>
+template <int ID0, int TO, int TI, int ACC, int NWV>
 __device__ __forceinline__ void write_dw_layer(float* dst, int rows, int in, const v4f (&acc)[ACC], int w, int lane) {
   const int j = lane & 15, g = lane >> 4;
 #pragma unroll
   for (int t = 0; t < TO * TI; ++t) {
     const int id = ID0 + t;
-    if (id % BWD_WAVES != w) continue;
+    if (id % NWV != w) continue;
     const int ot = t / TI, it = t % TI;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = 16 * ot + 4 * g + r, col = 16 * it + j;
-      if (row < rows && col < in) dst[row * in + col] = acc[id / BWD_WAVES][r];
+      if (row < rows && col < in) dst[row * in + col] = acc[id / NWV][r];
     }
   }
 }
 
-template <class Sh, int ACC>
+template <class Sh, int ACC, int NWV>
 __device__ void write_dw(float* part, const v4f (&acc)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TH = Sh::HID / 16;
   // geometry MLP
   float* dst = part;
-  write_dw_layer<0, Sh::NT, B::TI_GEO1, ACC>(dst, Sh::HID, Sh::IN_GEO, acc, w, lane);
+  write_dw_layer<0, Sh::NT, B::TI_GEO1, ACC, NWV>(dst, Sh::HID, Sh::IN_GEO, acc, w, lane);
   dst += Sh::HID * Sh::IN_GEO;
   constexpr int G1 = Sh::NT * B::TI_GEO1;
   if constexpr (Sh::NH == 2) {
-    write_dw_layer<G1, Sh::NT, TH, ACC>(dst, Sh::HID, Sh::HID, acc, w, lane);
+    write_dw_layer<G1, Sh::NT, TH, ACC, NWV>(dst, Sh::HID, Sh::HID, acc, w, lane);
     dst += Sh::HID * Sh::HID;
   }
   constexpr int G2 = G1 + (Sh::NH - 1) * Sh::NT * TH;
-  write_dw_layer<G2, 1, TH, ACC>(dst, HYRF_GEO_OUT, Sh::HID, acc, w, lane);
+  write_dw_layer<G2, 1, TH, ACC, NWV>(dst, HYRF_GEO_OUT, Sh::HID, acc, w, lane);
   dst += HYRF_GEO_OUT * Sh::HID;
   // colour MLP
   constexpr int C0 = B::TILES_GEO;
-  write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
+  write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC, NWV>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
   dst += Sh::HID * Sh::IN_COL;
   constexpr int C1 = C0 + Sh::NT * B::TI_COL1;
   if constexpr (Sh::NH == 2) {
-    write_dw_layer<C1, Sh::NT, TH, ACC>(dst, Sh::HID, Sh::HID, acc, w, lane);
+    write_dw_layer<C1, Sh::NT, TH, ACC, NWV>(dst, Sh::HID, Sh::HID, acc, w, lane);
     dst += Sh::HID * Sh::HID;
   }
   constexpr int C2 = C1 + (Sh::NH - 1) * Sh::NT * TH;
-  write_dw_layer<C2, 1, TH, ACC>(dst, HYRF_COL_OUT, Sh::HID, acc, w, lane);
+  write_dw_layer<C2, 1, TH, ACC, NWV>(dst, HYRF_COL_OUT, Sh::HID, acc, w, lane);
 }
 
 // Contraction Jacobian transpose: dL/dp from dL/dx (App. A.1 map).
@@ -424,23 +424,42 @@ __device__ __forceinline__ void map_or_global_add(uint32_t* mk, float2* mv, floa
   if (v1 != 0.f) atomicAdd(tr + 1, v1);
 }
 
+// Waves per workgroup.  Background pixels run only the colour decoder: its
+// weights and the staging of 8 waves fit LDS, and 8 waves hide latency.
+// Gaussians run both decoders: with 4 waves the staging shrinks enough that
+// both decoders' weights sit in LDS too.
+template <bool RAY>
+constexpr int bwd_waves() { return RAY ? 8 : 4; }
+
 template <class Sh, bool RAY, class TT, bool BF>
-__global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
+__global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArgs a) {
   using B = BwdShape<Sh>;
   using D = Dec<Sh, BF>;
-  constexpr int ACC = B::ACC;
-  __shared__ __attribute__((aligned(16))) float Xs[POINTS_PER_ROUND * STAGE_W];
-  __shared__ __attribute__((aligned(16))) float Ys[POINTS_PER_ROUND * STAGE_W];
+  constexpr int NWV = bwd_waves<RAY>();
+  constexpr int NT = NWV * 64;
+  constexpr int PPR = NWV * 16;   // points per round
+  constexpr int ACC = B::template ACC<NWV>;
+  __shared__ __attribute__((aligned(16))) float Xs[PPR * STAGE_W];
+  __shared__ __attribute__((aligned(16))) float Ys[PPR * STAGE_W];
   // the colour decoder's permuted weights (forward and adjoint operand
   // orders; float32 or bfloat16 bytes) live in LDS for the whole persistent
   // loop: every MFMA A operand is then an LDS read, not an L2 round trip
   __shared__ __attribute__((aligned(16))) float s_wf_col[Sh::W_COL];
   __shared__ __attribute__((aligned(16))) float s_wb_col[B::WB_COL];
+  // the geometry decoder's too, for the Gaussians
+  __shared__ __attribute__((aligned(16))) float s_wf_geo[RAY ? 4 : Sh::W_GEO];
+  __shared__ __attribute__((aligned(16))) float s_wb_geo[RAY ? 4 : B::WB_GEO];
   {
     const float4* src_f = reinterpret_cast<const float4*>(a.wf_col);
     const float4* src_b = reinterpret_cast<const float4*>(a.wb_col);
-    for (int i = threadIdx.x; i < Sh::W_COL / 4; i += BWD_NT) reinterpret_cast<float4*>(s_wf_col)[i] = src_f[i];
-    for (int i = threadIdx.x; i < B::WB_COL / 4; i += BWD_NT) reinterpret_cast<float4*>(s_wb_col)[i] = src_b[i];
+    for (int i = threadIdx.x; i < Sh::W_COL / 4; i += NT) reinterpret_cast<float4*>(s_wf_col)[i] = src_f[i];
+    for (int i = threadIdx.x; i < B::WB_COL / 4; i += NT) reinterpret_cast<float4*>(s_wb_col)[i] = src_b[i];
+    if constexpr (!RAY) {
+      const float4* gf = reinterpret_cast<const float4*>(a.wf_geo);
+      const float4* gb = reinterpret_cast<const float4*>(a.wb_geo);
+      for (int i = threadIdx.x; i < Sh::W_GEO / 4; i += NT) reinterpret_cast<float4*>(s_wf_geo)[i] = gf[i];
+      for (int i = threadIdx.x; i < B::WB_GEO / 4; i += NT) reinterpret_cast<float4*>(s_wb_geo)[i] = gb[i];
+    }
     __syncthreads();
   }
   const int lane = lane_id();
@@ -451,7 +470,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   for (int k = 0; k < ACC; ++k) accW[k] = v4f{0.f, 0.f, 0.f, 0.f};
   const int HW = a.W * a.H;
   const int count = RAY ? a.cams.V * HW : *a.count;
-  const int rounds = (count + POINTS_PER_ROUND - 1) / POINTS_PER_ROUND;
+  const int rounds = (count + PPR - 1) / PPR;
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const int V = a.cams.V;
   // Gaussians: rounds strided over workgroups; background pixels: each
@@ -462,7 +481,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
   const int r_end = RAY ? min(rounds, r_begin + per_blk) : rounds;
   const int r_step = RAY ? 1 : (int)gridDim.x;
   for (int round = r_begin; round < r_end; round += r_step) {
-    const int item = round * POINTS_PER_ROUND + w * 16 + j;
+    const int item = round * PPR + w * 16 + j;
     const bool valid = item < count;
     float fg[Sh::FPL], fr[Sh::FPL];
     double x[3];
@@ -494,7 +513,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       for (int s = 0; s < D::SG; ++s) x1g[s] = s < Sh::FPL ? fg[s] : 0.f;
       float hg[Sh::NH][Sh::S_HID];
       v4f og;
-      D::template fwd<D::SG>(a.wf_geo, x1g, hg, og, lane);
+      D::template fwd<D::SG>(s_wf_geo, x1g, hg, og, lane);
       v4f dg = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         const float* d = a.dgeo + (size_t)item * 8;
@@ -522,7 +541,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
 #pragma unroll
           for (int k = 0; k < 4; ++k) a.g_rot_e[(size_t)k * a.n + gi] += dr[k];
       }
-      D::template bwd<false, D::SG, ACC>(a.wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
+      D::template bwd<false, D::SG, ACC, NWV>(s_wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
     } else {
       pix = valid ? item : 0;
       v_r = pix / HW;
@@ -588,7 +607,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
         }
       }
       float dxc[D::SC];
-      D::template bwd<true, D::SC, ACC>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+      D::template bwd<true, D::SC, ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
       for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
       if constexpr (!RAY) {
@@ -651,7 +670,7 @@ __global__ __launch_bounds__(BWD_NT) void k_field_bwd(FieldBwdArgs a) {
       }
     }
   }
-  write_dw<Sh, ACC>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
+  write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
 // ---- cell-run scatter of a level's 8 corners x 2 features
@@ -950,11 +969,12 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     k_composite_bwd<<<grid, 256, 0, st>>>(L.comp);
     k_project_bwd<<<nblk(L.proj.n > 0 ? L.proj.n : 1), 256, 0, st>>>(L.proj);
   }
-  if (L.stages & BWD_STAGE_DECODERS) k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, BWD_NT, 0, st>>>(a);
+  if (L.stages & BWD_STAGE_DECODERS)
+    k_field_bwd<Sh, false, TT, BF><<<L.blocks_g, bwd_waves<false>() * 64, 0, st>>>(a);
   if ((L.stages & BWD_STAGE_BG_DECODERS) && L.with_bg) {
     FieldBwdArgs b = a;
     b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
-    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, BWD_NT, 0, st>>>(b);
+    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, bwd_waves<true>() * 64, 0, st>>>(b);
   }
   if (L.stages & BWD_STAGE_DW) {
     const int parts = L.blocks_g + (L.with_bg ? L.blocks_r : 0);

@@ -7,7 +7,7 @@
 //    own input order (row 16*ot + 4g + r <-> the lane's input s = 4*ot + r).
 //  * dW = sum over points of dY (x) X needs the point index on the MFMA's k
 //    axis, i.e. across lane groups: the workgroup stages X and dY of its
-//    POINTS_PER_ROUND points in LDS ([point][feature], column-swizzled) and
+//    NWV * 16 points in LDS ([point][feature], column-swizzled) and
 //    every wave accumulates a fixed subset of the 16x16 dW tiles over all
 //    staged points in registers, across every round of the persistent loop.
 #pragma once
@@ -15,9 +15,8 @@
 
 namespace hyrf {
 
-constexpr int BWD_WAVES = 8;
-constexpr int BWD_NT = BWD_WAVES * 64;
-constexpr int POINTS_PER_ROUND = BWD_WAVES * 16;
+// Waves per workgroup (NWV) is a template parameter of the adjoint: a
+// workgroup stages NWV * 16 points per round.
 constexpr int STAGE_W = 64;                    // staged feature columns
 
 template <class Sh>
@@ -29,7 +28,8 @@ struct BwdShape {
   static constexpr int TILES_GEO = Sh::NT * TI_GEO1 + (Sh::NH - 1) * Sh::NT * TI_H + TI_H;
   static constexpr int TILES_COL = Sh::NT * TI_COL1 + (Sh::NH - 1) * Sh::NT * TI_H + TI_H;
   static constexpr int TILES = TILES_GEO + TILES_COL;
-  static constexpr int ACC = (TILES + BWD_WAVES - 1) / BWD_WAVES;   // tiles per wave
+  template <int NWV>
+  static constexpr int ACC = (TILES + NWV - 1) / NWV;   // dW tiles per wave
   // backward-permuted weight floats per MLP
   static constexpr int WB_GEO = Sh::NT * 4 * 64 + (Sh::NH - 1) * Sh::NT * Sh::S_HID * 64 +
                                 (Sh::S_GEO1 / 4) * Sh::S_HID * 64;
@@ -110,24 +110,24 @@ __device__ __forceinline__ int swz(int row, int col) { return row * STAGE_W + (c
 
 // Accumulate the dW tiles of one layer from the staged [point][feature]
 // arrays: tile (ot, it) += sum_p Y[p][16 ot + i] X[p][16 it + j].
-// Tile ids TB .. TB + TO*TI - 1; wave w owns ids with id % BWD_WAVES == w.
-template <int TB, int TO, int TI, int ACC>
+// Tile ids TB .. TB + TO*TI - 1; wave w owns ids with id % NWV == w.
+template <int TB, int TO, int TI, int ACC, int NWV>
 __device__ __forceinline__ void dw_tiles(const float* Xs, const float* Ys, v4f (&acc)[ACC], int w, int lane) {
   const int kk = lane >> 4, i = lane & 15;
 #pragma unroll
   for (int t = 0; t < TO * TI; ++t) {
     const int id = TB + t;
-    if (id % BWD_WAVES != w) continue;
+    if (id % NWV != w) continue;
     const int ot = t / TI, it = t % TI;
-    v4f c = acc[id / BWD_WAVES];
+    v4f c = acc[id / NWV];
 #pragma unroll 8
-    for (int s = 0; s < POINTS_PER_ROUND / 4; ++s) {
+    for (int s = 0; s < NWV * 16 / 4; ++s) {
       const int p = 4 * s + kk;
       const float av = Ys[swz(p, 16 * ot + i)];
       const float bv = Xs[swz(p, 16 * it + i)];
       c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
     }
-    acc[id / BWD_WAVES] = c;
+    acc[id / NWV] = c;
   }
 }
 
@@ -153,7 +153,7 @@ __device__ __forceinline__ void stage_inputs(float* S, int pt, int g, const floa
 // gradient tile (lane holds rows 4g..4g+3).  Returns dx (lane input order).
 // Contains workgroup barriers: every thread of the workgroup must call it
 // with the same template arguments.  TB0: first dW tile id of this MLP.
-template <class Sh, bool COL, int S1, int ACC>
+template <class Sh, bool COL, int S1, int ACC, int NWV>
 __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const float (&x1)[S1],
                                              const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                              float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
@@ -173,7 +173,7 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
   }
   __syncthreads();
   constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
-  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
   float dh[Sh::S_HID];
   {
@@ -193,7 +193,7 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
     stage_units<Sh::S_HID>(Xs, pt, g, h[k - 1]);
     __syncthreads();
     constexpr int TB_H = TB0 + Sh::NT * TI1;
-    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
     __syncthreads();
     v4f acc[Sh::NT];
     mfma_layer<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
@@ -207,7 +207,7 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
   stage_units<Sh::S_HID>(Ys, pt, g, dh);
   stage_inputs<Sh, S1>(Xs, pt, g, x1, colour);
   __syncthreads();
-  dw_tiles<TB0, Sh::NT, TI1, ACC>(Xs, Ys, accW, w, lane);
+  dw_tiles<TB0, Sh::NT, TI1, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
   {
     v4f acc[S1 / 4];
@@ -294,7 +294,7 @@ __device__ __forceinline__ void stage_units_bf(float* S, int pt, int g, const fl
         make_float4(bf16r(v[4 * b]), bf16r(v[4 * b + 1]), bf16r(v[4 * b + 2]), bf16r(v[4 * b + 3]));
 }
 
-template <class Sh, bool COL, int S1, int ACC>
+template <class Sh, bool COL, int S1, int ACC, int NWV>
 __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb, const float (&x1)[S1],
                                                   const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                                   float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
@@ -310,7 +310,7 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
   stage_units_bf<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
   __syncthreads();
   constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
-  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+  dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
   float dh[Sh::S_HID];
   {
@@ -329,7 +329,7 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
     stage_units_bf<Sh::S_HID>(Xs, pt, g, h[k - 1]);
     __syncthreads();
     constexpr int TB_H = TB0 + Sh::NT * TI1;
-    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC>(Xs, Ys, accW, w, lane);
+    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
     __syncthreads();
     v4f acc[Sh::NT];
     mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
@@ -346,7 +346,7 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
     if (col >= 0) Xs[swz(pt, col)] = bf16r(x1[s]);
   }
   __syncthreads();
-  dw_tiles<TB0, Sh::NT, TI1, ACC>(Xs, Ys, accW, w, lane);
+  dw_tiles<TB0, Sh::NT, TI1, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
   {
     v4f acc[S1 / 4];
