@@ -224,8 +224,7 @@ def main():
     ms_train, ev_t, (st, loss) = timed(train_step, args.steps)
     bwd_keys = (("backward", "bwd0", "bwd1"), ("bwd_splats", "bwd_stage1", "bwd_stage2"),
                 ("bwd_decoders", "bwd_stage2", "bwd_stage3"), ("bwd_tables", "bwd_stage3", "bwd_gauss_end"),
-                ("bwd_bg_decoders", "bwd_stage4", "bwd_stage5"), ("bwd_bg_tables", "bwd_stage5", "bwd_bg_end"),
-                ("bwd_dw", "bwd_stage6", "bwd_stage7"))
+                ("bwd_bg", "bwd_stage4", "bwd_bg_end"), ("bwd_dw", "bwd_stage6", "bwd_stage7"))
     st_train = stages(ev_t, fwd_keys + bwd_keys)
     print(f"[bench] train step {ms_train:.3f} ms; stages (branches overlapped) {st_train}; loss {float(loss):.5f}; "
           f"entries {st.n_entries}", file=sys.stderr, flush=True)
@@ -233,8 +232,8 @@ def main():
     ms_train_serial, ev_s, _ = timed(lambda ev: train_step(ev, overlap=False), args.steps)
     ser_keys = (("backward", "bwd0", "bwd1"), ("bwd_weights", "bwd_stage0", "bwd_stage1"),
                 ("bwd_splats", "bwd_stage1", "bwd_stage2"), ("bwd_decoders", "bwd_stage2", "bwd_stage3"),
-                ("bwd_tables", "bwd_stage3", "bwd_stage4"), ("bwd_bg_decoders", "bwd_stage4", "bwd_stage5"),
-                ("bwd_bg_tables", "bwd_stage5", "bwd_stage6"), ("bwd_dw", "bwd_stage6", "bwd_stage7"))
+                ("bwd_tables", "bwd_stage3", "bwd_stage4"), ("bwd_bg", "bwd_stage4", "bwd_stage5"),
+                ("bwd_dw", "bwd_stage6", "bwd_stage7"))
     st_serial = stages(ev_s, fwd_keys + ser_keys)
     print(f"[bench] train step, stages serial {ms_train_serial:.3f} ms; stages {st_serial}", file=sys.stderr,
           flush=True)
@@ -314,13 +313,14 @@ def main():
     del dq, dqb
 
     # Roofline of the dominant kernel of the train step: the background
-    # points' radiance-table adjoint (k_bg_grid_bwd, alone in backward stage
-    # 5 of the serial run).  Algorithmic bytes per background pixel: its feature gradient read
-    # (2L floats) + for each of L levels x 8 corners one read-modify-write of
-    # the 2-float table row (16 B).
+    # points' adjoint (k_field_bwd in ray mode: colour decoder on MFMA, then
+    # the radiance-table scatter; alone in backward stage 4 of the serial
+    # run).  Algorithmic bytes per background pixel: the saved features read
+    # (2L floats), T_final and dL/dC read (4 floats), and for each of L
+    # levels x 8 corners one read-modify-write of the 2-float table row (16 B).
     n_bg = V * H * W
-    per_px = 2 * cfg.levels * 4 + cfg.levels * 8 * 16
-    bg_ms = st_serial["bwd_bg_tables"]
+    per_px = 2 * cfg.levels * 4 + 4 * 4 + cfg.levels * 8 * 16
+    bg_ms = st_serial["bwd_bg"]
     ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
     # the scatter's real bound: float atomics.  Reference rate: torch's
     # index_add_ of 64M values at random indices of a 256 MB buffer (one
@@ -342,8 +342,9 @@ def main():
     atomics = {"float_adds_per_launch": adds, "adds_per_s": round(adds / (bg_ms * 1e-3) / 1e9, 1),
                "random_atomics_per_s_measured": round(atomic_rate / 1e9, 1), "unit": "G/s",
                "reference": "torch index_add_, 64M values at random indices of 64M floats"}
-    roof = {"kernel": "k_bg_grid_bwd", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic("k_bg_grid_bwd"),
+    roof = {"kernel": "k_field_bwd (background points)", "bound": "hbm", "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("k_field_bwd_bg"),
             "algorithmic_bytes": n_bg * per_px,
             "bytes_per_pixel": per_px, "pixels": n_bg, "kernel_ms": round(bg_ms, 4),
             "share_of_step": round(bg_ms / ms_train, 3), "atomics": atomics}

@@ -276,7 +276,8 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
 
 /* The same adjoint split into seven stages, for callers that overlap or time
  * them.  Every stage takes the same arguments and workspace; each reads what
- * the stages it depends on left in the workspace:
+ * the stages it depends on left in the workspace (stage numbers are stable;
+ * stage 5 is empty since stage 4 scatters its table gradients itself):
  *   0  decoder weights permuted into the operand order of the adjoint
  *   1  blending and projection adjoints (explicit-parameter gradients,
  *      densification statistics)
@@ -284,8 +285,9 @@ hyrf_status hyrf_render_backward(const hyrf_fields* fields, const hyrf_gaussians
  *      and, with saved feature derivatives, through the interpolation
  *      weights                                                    (after 0, 1)
  *   3  hash-table adjoint of the Gaussians                         (after 2)
- *   4  colour-decoder adjoint of the background points             (after 0)
- *   5  radiance-table adjoint of the background points             (after 4)
+ *   4  colour-decoder and radiance-table adjoints of the background
+ *      points                                                     (after 0)
+ *   5  launches nothing                                            (after 4)
  *   6  decoder weight gradients from the partials of 2 and 4   (after 2, 4)
  * The Gaussian branch (1, 2, 3) and the background branch (4, 5) touch
  * disjoint workspace regions and meet only in atomic additions to the

@@ -407,11 +407,11 @@ namespace {
 constexpr int BWD_MAX_BLOCKS = 256;   // persistent: one 8-wave workgroup per CU
 
 struct BwdWs {
-  float *gs, *dgeo, *dcol, *dfeat_geo, *dfeat_rad, *dfeat_bg, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;
+  float *gs, *dgeo, *dcol, *dfeat_geo, *dfeat_rad, *wf_geo, *wf_col, *wb_geo, *wb_col, *dw_part;
   size_t bytes;
 };
 
-BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max, int64_t pixels) {
+BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max) {
   size_t fg = 0, fc = 0, bg = 0, bc = 0, nw = 0;
   bwd_weight_floats(f->levels, f->hidden, f->n_hidden, &fg, &fc, &bg, &bc, &nw);
   Carve c(base);
@@ -422,7 +422,6 @@ BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max, int64_t pixe
   w.dcol = c.take<float>(nm * V * 3);
   w.dfeat_geo = c.take<float>(nm * 2 * f->levels);
   w.dfeat_rad = c.take<float>(nm * 2 * f->levels);
-  w.dfeat_bg = c.take<float>((size_t)(pixels > 0 ? pixels : 1) * 2 * f->levels);
   w.wf_geo = c.take<float>(fg);
   w.wf_col = c.take<float>(fc);
   w.wb_geo = c.take<float>(bg);
@@ -436,7 +435,7 @@ BwdWs carve_bwd(void* base, const hyrf_fields* f, int V, int n_max, int64_t pixe
 size_t hyrf_backward_workspace_bytes(const hyrf_fields* fields, int32_t n_views, int32_t n_max, int32_t width,
                                      int32_t height) {
   if (!fields || !shape_supported(fields->levels, fields->hidden, fields->n_hidden) || n_views < 1) return 0;
-  return carve_bwd(nullptr, fields, n_views, n_max, (int64_t)n_views * width * height).bytes;
+  return carve_bwd(nullptr, fields, n_views, n_max).bytes;
 }
 
 static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hyrf_gaussians* g,
@@ -465,7 +464,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   const size_t need = hyrf_backward_workspace_bytes(fields, n_views, sp->n_max, cams[0].width, cams[0].height);
   REQ(ws && ws_bytes >= need, "backward workspace too small: %zu < %zu bytes", ws_bytes, need);
   hipStream_t st = (hipStream_t)stream;
-  BwdWs w = carve_bwd(ws, fields, n_views, sp->n_max, (int64_t)n_views * cams[0].width * cams[0].height);
+  BwdWs w = carve_bwd(ws, fields, n_views, sp->n_max);
   const int W = cams[0].width, H = cams[0].height;
   BwdLaunch L{};
   L.stages = stages;
@@ -523,7 +522,6 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.dcol = w.dcol;
   F.dfeat_geo = w.dfeat_geo;
   F.dfeat_rad = w.dfeat_rad;
-  F.dfeat_bg = w.dfeat_bg;
   F.g_pos = grads->pos;
   F.g_rot_e = grads->rot_e;
   F.g_table_geo = fields->single_field ? nullptr : grads->table_geo;

@@ -69,7 +69,6 @@ struct FieldBwdArgs {
   const float* dcol;
   float* dfeat_geo;      // [n][2L] feature gradients handed to the grid adjoint
   float* dfeat_rad;
-  float* dfeat_bg;       // [V*H*W][2L] background feature gradients
   float* g_pos;
   float* g_rot_e;
   float* g_table_geo;
@@ -99,25 +98,18 @@ struct GridBwdArgs {
   float* g_table_rad;
 };
 
-struct BgGridArgs {
-  GridP grid;
-  Cams cams;
-  int W, H;
-  const float* dfeat_bg;
-  float* g_table_rad;
-};
-
 // Stages of the adjoint.  WEIGHTS first; then two independent branches --
-// Gaussians (SPLATS, DECODERS, TABLES) and background points (BG_DECODERS,
-// BG_TABLES) -- which may run concurrently on two streams; DW after both
-// decoder stages.
+// Gaussians (SPLATS, DECODERS, TABLES) and background points (BG_DECODERS;
+// BG_TABLES launches nothing since the background decoder adjoint scatters
+// its table gradients itself) -- which may run concurrently on two streams;
+// DW after both decoder stages.
 enum : int {
   BWD_STAGE_WEIGHTS = 1,       // decoder weights permuted into the MFMA operand order
   BWD_STAGE_SPLATS = 2,        // blending + projection adjoints
   BWD_STAGE_DECODERS = 4,      // decoder adjoints of the Gaussians -> dW partials, feature grads
   BWD_STAGE_TABLES = 8,        // Gaussians' hash-table adjoint -> table grads
-  BWD_STAGE_BG_DECODERS = 16,  // colour-decoder adjoint of the background points
-  BWD_STAGE_BG_TABLES = 32,    // background points' radiance-table adjoint
+  BWD_STAGE_BG_DECODERS = 16,  // colour-decoder + radiance-table adjoint of the background points
+  BWD_STAGE_BG_TABLES = 32,    // empty (kept so that stage numbers stay stable)
   BWD_STAGE_DW = 64,           // dW partials -> decoder weight gradients
   BWD_STAGE_ALL = 127
 };

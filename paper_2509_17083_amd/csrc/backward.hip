@@ -10,11 +10,13 @@
 //  k_field_bwd      per 16 Gaussians per wave (or 16 background pixels):
 //                   decoder adjoints on MFMA with dW accumulated through LDS
 //                   staging; feature gradients out, plus the view-direction
-//                   part of the position gradient.
+//                   part of the position gradient.  For background pixels
+//                   the radiance-table scatter-add follows in the same
+//                   kernel, round by round.
 //  k_grid_bwd       per Gaussian: hash-table scatter-add (cell runs summed,
-//                   lane-combined atomics) and the position gradient through
-//                   the interpolation weights and the contraction.
-//  k_bg_grid_bwd    per background pixel: radiance-table scatter-add.
+//                   lane-combined atomics) and, when the forward saved no
+//                   feature derivatives, the position gradient through the
+//                   interpolation weights and the contraction.
 //  k_dw_reduce      sums the per-workgroup dW partials in a fixed order.
 #include "backward.h"
 #include "block.h"
@@ -394,34 +396,140 @@ __device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py
   for (int d = 0; d < 3; ++d) dp[d] = dq[d] * gp.inv_half[d];
 }
 
-constexpr int MAP_SLOTS = 2048;
-constexpr int BG_GRID_BLOCKS = 1024;   // persistent: 4 workgroups per CU, each a contiguous pixel band
-constexpr uint32_t MAP_EMPTY = 0xFFFFFFFFu;
-constexpr int MAP_MAX_RES = 182;   // levels up to this resolution use the workgroup map
+// ---- cell-run scatter of a level's 8 corners x 2 features
+//
+// A float atomic costs one memory request per 64-byte line touched by a wave
+// instruction: lanes of one instruction that hit the same line combine, lanes
+// that hit the same ADDRESS do not, and requests to distinct lines issue at
+// one per clock of the memory-side atomic units.  So the table adjoints (1)
+// sum, in registers, the contributions of consecutive lanes whose points lie
+// in the same grid cell (runs: spatially ordered Gaussians, adjacent pixels),
+// then (2) stage each run total's 16 floats in LDS and issue them 16 lanes
+// per cell, corner-major: corners c and c^1 differ in x only and are adjacent
+// rows whenever the cell's x index is even, so one instruction touches a few
+// lines per cell instead of one line per float.
+constexpr int STAGE_CELLS = 32;   // run totals staged per wave and pass
 
-// Add (v0, v1) to table row `row` of level `lev`: through the workgroup map
-// when `use_map` (linear probing, at most 8 slots), else (or when the probe
-// finds no slot) with global atomics.
-__device__ __forceinline__ void map_or_global_add(uint32_t* mk, float2* mv, float* gtab, int lev, uint32_t T,
-                                                  uint32_t row, float v0, float v1, bool use_map) {
-  if (v0 == 0.f && v1 == 0.f) return;
-  const uint32_t key = (uint32_t)lev * T + row;
-  if (use_map) {
-    uint32_t h = (key * 2654435761u) >> (32 - 11);
-#pragma unroll 1
-    for (int probe = 0; probe < 8; ++probe) {
-      const uint32_t prev = atomicCAS(&mk[h], MAP_EMPTY, key);
-      if (prev == MAP_EMPTY || prev == key) {
-        atomicAdd(&mv[h].x, v0);
-        atomicAdd(&mv[h].y, v1);
-        return;
-      }
-      h = (h + 1) & (MAP_SLOTS - 1);
+struct CellStage {
+  uint32_t idx[STAGE_CELLS * 16];
+  float val[STAGE_CELLS * 16];
+};
+
+__device__ __forceinline__ void wave_lds_sync() {
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Lanes whose cell differs from the previous lane's (lane 0 always).
+__device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
+  const int lane = lane_id();
+  const int p0 = __shfl_up(ci[0], 1, 64), p1 = __shfl_up(ci[1], 1, 64), p2 = __shfl_up(ci[2], 1, 64);
+  return __ballot(lane == 0 || p0 != ci[0] || p1 != ci[1] || p2 != ci[2]);
+}
+
+// Segmented inclusive sums of v over the runs that start at the set bits of
+// `heads`: the last lane of every run ends with the run's totals.
+template <int N>
+__device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
+  if (heads == ~0ull) return;   // every lane its own run
+  const int lane = lane_id();
+  const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
+  const int head = 63 - __clzll((long long)upto);
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const float t = __shfl_up(v[k], off, 64);
+      if (lane - off >= head) v[k] += t;
     }
   }
-  float* tr = gtab + (size_t)key * 2;
-  if (v0 != 0.f) atomicAdd(tr, v0);
-  if (v1 != 0.f) atomicAdd(tr + 1, v1);
+}
+
+// Add the run totals of one level to a table-gradient level g ([T][2]):
+// the last lane of each run holds 16 floats, row[c] * 2 + f <- v[2c + f].
+// Every lane of the wave must call it.
+__device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t heads, const uint32_t (&row)[8],
+                                              const float* v, CellStage& st) {
+  const int lane = lane_id();
+  const uint64_t tails = (heads >> 1) | (1ull << 63);
+  const bool tail = (tails >> lane) & 1ull;
+  const int rank = __popcll(tails & ((1ull << lane) - 1ull));
+  const int K = __popcll(tails);
+  for (int b = 0; b < K; b += STAGE_CELLS) {
+    if (tail && rank >= b && rank < b + STAGE_CELLS) {
+      const int base = (rank - b) * 16;
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        st.idx[base + 2 * c] = row[c] * 2u;
+        st.idx[base + 2 * c + 1] = row[c] * 2u + 1u;
+        st.val[base + 2 * c] = v[2 * c];
+        st.val[base + 2 * c + 1] = v[2 * c + 1];
+      }
+    }
+    wave_lds_sync();
+    const int n = min(K - b, STAGE_CELLS) * 16;
+    for (int s2 = lane; s2 < n; s2 += 64) {
+      const float x = st.val[s2];
+      if (x != 0.f) atomicAdd(g + st.idx[s2], x);
+    }
+    wave_lds_sync();
+  }
+}
+
+
+
+// Radiance-table scatter of one round of background pixels, inside the
+// background decoder adjoint (Sec. 3.3): the round's feature gradients sit
+// in LDS ([pixel][BG_DF_STRIDE], pixel-major), and the 8 waves split the
+// work as 2 halves of 64 consecutive pixels x 4 level groups (levels
+// lg, lg + 4, ...).  Each lane recomputes its pixel's contracted sphere
+// point in float64, so the cells match the forward gather exactly.  The
+// atomics do not return: they drain while the next round's MFMA work runs.
+constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
+
+template <int L>
+__device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, int first, int count, const float* sdf,
+                                                 CellStage& st, int w) {
+  static_assert(2 * L + 2 <= BG_DF_STRIDE, "LDS row too short");
+  const int lane = lane_id();
+  const int pl = (w & 1) * 64 + lane;
+  const int lg = w >> 1;
+  const int item = first + pl;
+  const bool valid = item < count;
+  const int pix = valid ? item : 0;
+  const int HW = a.W * a.H;
+  const int v = pix / HW;
+  const int rem = pix - v * HW;
+  const int yy = rem / a.W, xx = rem - yy * a.W;
+  double ps[3], d[3], x[3];
+  sphere_point_f64(a.cams.c[v], xx, yy, (double)a.grid.bg_radius, ps, d);
+  contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+  const uint32_t Tr = a.grid.mask_rad + 1u;
+#pragma unroll 1
+  for (int k = 0; k < L / 4; ++k) {
+    const int lev = lg + 4 * k;
+    const int res = a.grid.res[lev];
+    int ci[3];
+    float wv[3];
+    grid_cell(x, res, ci, wv);
+    const uint32_t side = (uint32_t)res + 1u;
+    const bool drn = (a.grid.dense_rad >> lev) & 1u;
+    const float2 df = *reinterpret_cast<const float2*>(sdf + pl * BG_DF_STRIDE + 2 * lev);
+    uint32_t row[8];
+    float sv[16];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+      const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
+      row[c] = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
+                          a.grid.mask_rad);
+      sv[2 * c] = wc * df.x;
+      sv[2 * c + 1] = wc * df.y;
+    }
+    const uint64_t heads = cell_heads(ci);
+    run_sums<16>(heads, sv);
+    scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, row, sv, st);
+  }
 }
 
 // Waves per workgroup.  Background pixels run only the colour decoder: its
@@ -661,103 +769,28 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
 #pragma unroll
         for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k] + dpw[k];
       }
-    } else if (valid) {
-      // background points: feature gradients handed to the background grid adjoint
+    } else if (a.g_table_rad) {
+      // background points: the round's feature gradients to LDS (the dW
+      // staging is free once every wave has left the decoder adjoint), then
+      // the radiance-table scatter of the round
+      static_assert(NWV == 8 && PPR * BG_DF_STRIDE <= PPR * STAGE_W && NWV * sizeof(CellStage) <= sizeof(Xs),
+                    "background scatter layout");
+      __syncthreads();
+      const int pl = w * 16 + j;
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
-        *reinterpret_cast<float2*>(a.dfeat_bg + (size_t)pix * 2 * Sh::L + 2 * lev) = make_float2(dfr[2 * k], dfr[2 * k + 1]);
+        *reinterpret_cast<float2*>(Ys + pl * BG_DF_STRIDE + 2 * lev) =
+            valid ? make_float2(dfr[2 * k], dfr[2 * k + 1]) : make_float2(0.f, 0.f);
       }
+      __syncthreads();
+      bg_round_scatter<Sh::L>(a, round * PPR, count, Ys, reinterpret_cast<CellStage*>(Xs)[w], w);
+      __syncthreads();
     }
   }
   write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
-// ---- cell-run scatter of a level's 8 corners x 2 features
-//
-// A float atomic costs one memory request per 64-byte line touched by a wave
-// instruction: lanes of one instruction that hit the same line combine, lanes
-// that hit the same ADDRESS do not, and requests to distinct lines issue at
-// one per clock of the memory-side atomic units.  So the table adjoints (1)
-// sum, in registers, the contributions of consecutive lanes whose points lie
-// in the same grid cell (runs: spatially ordered Gaussians, adjacent pixels),
-// then (2) stage each run total's 16 floats in LDS and issue them 16 lanes
-// per cell, corner-major: corners c and c^1 differ in x only and are adjacent
-// rows whenever the cell's x index is even, so one instruction touches a few
-// lines per cell instead of one line per float.
-constexpr int STAGE_CELLS = 32;   // run totals staged per wave and pass
-
-struct CellStage {
-  uint32_t idx[STAGE_CELLS * 16];
-  float val[STAGE_CELLS * 16];
-};
-
-__device__ __forceinline__ void wave_lds_sync() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-  __builtin_amdgcn_wave_barrier();
-}
-
-// Lanes whose cell differs from the previous lane's (lane 0 always).
-__device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
-  const int lane = lane_id();
-  const int p0 = __shfl_up(ci[0], 1, 64), p1 = __shfl_up(ci[1], 1, 64), p2 = __shfl_up(ci[2], 1, 64);
-  return __ballot(lane == 0 || p0 != ci[0] || p1 != ci[1] || p2 != ci[2]);
-}
-
-// Segmented inclusive sums of v over the runs that start at the set bits of
-// `heads`: the last lane of every run ends with the run's totals.
-template <int N>
-__device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
-  if (heads == ~0ull) return;   // every lane its own run
-  const int lane = lane_id();
-  const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
-  const int head = 63 - __clzll((long long)upto);
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-      const float t = __shfl_up(v[k], off, 64);
-      if (lane - off >= head) v[k] += t;
-    }
-  }
-}
-
-// Add the run totals of one level to a table-gradient level g ([T][2]):
-// the last lane of each run holds 16 floats, row[c] * 2 + f <- v[2c + f].
-// Every lane of the wave must call it.
-__device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t heads, const uint32_t (&row)[8],
-                                              const float* v, CellStage& st) {
-  const int lane = lane_id();
-  const uint64_t tails = (heads >> 1) | (1ull << 63);
-  const bool tail = (tails >> lane) & 1ull;
-  const int rank = __popcll(tails & ((1ull << lane) - 1ull));
-  const int K = __popcll(tails);
-  for (int b = 0; b < K; b += STAGE_CELLS) {
-    if (tail && rank >= b && rank < b + STAGE_CELLS) {
-      const int base = (rank - b) * 16;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        st.idx[base + 2 * c] = row[c] * 2u;
-        st.idx[base + 2 * c + 1] = row[c] * 2u + 1u;
-        st.val[base + 2 * c] = v[2 * c];
-        st.val[base + 2 * c + 1] = v[2 * c + 1];
-      }
-    }
-    wave_lds_sync();
-    const int n = min(K - b, STAGE_CELLS) * 16;
-    for (int s2 = lane; s2 < n; s2 += 64) {
-      const float x = st.val[s2];
-      if (x != 0.f) atomicAdd(g + st.idx[s2], x);
-    }
-    wave_lds_sync();
-  }
-}
-
-
-// Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
-// levels per lane: scatter-add of w_c * dL/df into both tables and
-// dL/dx = sum_c (dL/df . table[c]) dw_c/dx, then the contraction Jacobian ->
-// dL/dp.
 // Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
 // levels per lane: scatter-add of w_c * dL/df into both tables (cell runs of
 // consecutive Gaussians summed first; they share cells at the coarse levels
@@ -775,6 +808,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   if (blockIdx.x * 256 >= count) return;          // whole workgroup idle (uniform)
   const bool valid = item < count;
   const int gi = valid ? a.vis_idx[item] : 0;
+  const bool pos_done = a.pos_done;   // dL/dp through the weights added by the decoder adjoint
   float pxf = 0.f, pyf = 0.f, pzf = 0.f;
   if (valid) {
     pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
@@ -782,7 +816,6 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const bool single = a.grid.single != 0;
   const bool do_geo = a.g_table_geo && !single;
-  const bool pos_done = a.pos_done;   // dL/dp through the weights added by the decoder adjoint
   double x[3];
   contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
   float dxv[3] = {0.f, 0.f, 0.f};
@@ -849,84 +882,6 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
     contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
 #pragma unroll
     for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp[k];
-  }
-}
-
-// Radiance-table adjoint of the background points (Sec. 3.3): one lane per
-// pixel, 64 consecutive pixels of a row per wave, all levels per lane.  Runs
-// of consecutive pixels in the same cell are summed in registers first; the
-// coarsest levels then go through a workgroup-private map that each
-// persistent workgroup flushes once, the finer ones through the cell-staged
-// scatter.
-__global__ __launch_bounds__(256) void k_bg_grid_bwd(BgGridArgs a) {
-  __shared__ uint32_t map_key[MAP_SLOTS];
-  __shared__ float2 map_val[MAP_SLOTS];
-  __shared__ CellStage stage[4];
-  CellStage& st = stage[threadIdx.x / 64];
-  for (int k = threadIdx.x; k < MAP_SLOTS; k += 256) {
-    map_key[k] = MAP_EMPTY;
-    map_val[k] = make_float2(0.f, 0.f);
-  }
-  __syncthreads();
-  const int lane = lane_id();
-  const int HW = a.W * a.H;
-  const int64_t total = (int64_t)a.cams.V * HW;
-  const int64_t chunks = (total + 255) / 256;
-  const int64_t per_blk = (chunks + gridDim.x - 1) / gridDim.x;
-  const int64_t c0 = (int64_t)blockIdx.x * per_blk;
-  const int64_t c1 = min(chunks, c0 + per_blk);
-  const uint32_t Tr = a.grid.mask_rad + 1u;
-  for (int64_t ch = c0; ch < c1; ++ch) {
-    const int64_t pix64 = ch * 256 + threadIdx.x;
-    const bool valid = pix64 < total;
-    const int pix = valid ? (int)pix64 : 0;
-    const int v = pix / HW;
-    const int rem = pix - v * HW;
-    const int yy = rem / a.W, xx = rem - yy * a.W;
-    double ps[3], d[3], x[3];
-    sphere_point_f64(a.cams.c[v], xx, yy, (double)a.grid.bg_radius, ps, d);
-    contract_f64(a.grid, ps[0], ps[1], ps[2], x);
-    for (int lev = 0; lev < a.grid.L; ++lev) {
-      const int res = a.grid.res[lev];
-      int ci[3];
-      float wv[3];
-      grid_cell(x, res, ci, wv);
-      const uint32_t side = (uint32_t)res + 1u;
-      const bool drn = (a.grid.dense_rad >> lev) & 1u;
-      float2 df = make_float2(0.f, 0.f);
-      if (valid) df = *reinterpret_cast<const float2*>(a.dfeat_bg + (size_t)pix * 2 * a.grid.L + 2 * lev);
-      uint32_t row[8];
-      float sv[16];
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-        const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
-        row[c] = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
-                            a.grid.mask_rad);
-        sv[2 * c] = wc * df.x;
-        sv[2 * c + 1] = wc * df.y;
-      }
-      const uint64_t heads = cell_heads(ci);
-      run_sums<16>(heads, sv);
-      if (res <= MAP_MAX_RES) {
-        const bool tail = lane == 63 || ((heads >> (lane + 1)) & 1ull);
-        if (tail)
-#pragma unroll
-          for (int c = 0; c < 8; ++c)
-            map_or_global_add(map_key, map_val, a.g_table_rad, lev, Tr, row[c], sv[2 * c], sv[2 * c + 1], true);
-      } else {
-        scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, row, sv, st);
-      }
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < MAP_SLOTS; k += 256) {
-    const uint32_t key = map_key[k];
-    if (key != MAP_EMPTY) {
-      const float2 vv = map_val[k];
-      if (vv.x != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2, vv.x);
-      if (vv.y != 0.f) atomicAdd(a.g_table_rad + (size_t)key * 2 + 1, vv.y);
-    }
   }
 }
 
@@ -998,16 +953,8 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.g_table_rad = a.g_table_rad;
     k_grid_bwd<TT><<<(unsigned)((a.n + 255) / 256 > 0 ? (a.n + 255) / 256 : 1), 256, 0, st>>>(gb);
   }
-  if ((L.stages & BWD_STAGE_BG_TABLES) && L.with_bg && a.g_table_rad) {
-    BgGridArgs bg{};
-    bg.grid = a.grid;
-    bg.cams = a.cams;
-    bg.W = a.W;
-    bg.H = a.H;
-    bg.dfeat_bg = a.dfeat_bg;
-    bg.g_table_rad = a.g_table_rad;
-    k_bg_grid_bwd<<<BG_GRID_BLOCKS, 256, 0, st>>>(bg);
-  }
+  // BWD_STAGE_BG_TABLES: the background decoder adjoint scatters its table
+  // gradients itself; the stage launches nothing.
 }
 
 void launch_backward(int Lv, int hid, int nh, const BwdLaunch& L, hipStream_t st) {
