@@ -360,6 +360,81 @@ def main():
                 "traffic": measured_traffic("k_field_query"), "algorithmic_bytes": n_vis * per_g,
                 "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
 
+    # Measured denominators beside the vendor peaks: a plain device copy
+    # (HBM), a library FP32 / BF16 GEMM (MFMA) and the random float-atomic
+    # rate measured above.
+    src = torch.ones(256 << 20, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 4 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
+
+    def gemm_tflops(dtype):
+        a = torch.randn(8192, 8192, device="cuda").to(dtype)
+        b = torch.randn(8192, 8192, device="cuda").to(dtype)
+        torch.mm(a, b)
+        g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        g0.record()
+        for _ in range(5):
+            torch.mm(a, b)
+        g1.record()
+        torch.cuda.synchronize()
+        return 5 * 2 * 8192 ** 3 / (g0.elapsed_time(g1) * 1e-3) / 1e12
+    measured = {"hbm_copy_GBs": round(copy_gbs, 1), "fp32_gemm_TFLOPs": round(gemm_tflops(torch.float32), 1),
+                "bf16_gemm_TFLOPs": round(gemm_tflops(torch.bfloat16), 1),
+                "random_float_atomics_G_per_s": round(atomic_rate / 1e9, 1),
+                "how": "torch copy_ of 1 GiB (read + write); torch.mm 8192^3; torch index_add_ of 64M values "
+                       "at random indices"}
+
+    # Every stage against its own bound (FP32 fields, serial stage times),
+    # with the algorithmic work per unit of the method: bytes for the
+    # HBM-bound stages, VALU operations for blending, MFMA flops for the
+    # decoder adjoint.  VALU peak: 256 CUs x 64 lanes x 2.4 GHz (packed FP32
+    # is not used).
+    VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+    n_all = int(ds.n)
+    pairs = int(st.last.to(torch.int64).sum().item())
+    L_ = cfg.levels
+    mlp_fwd_flop = 13.3e3 + 15.7e3 * V       # geometry + colour decoder per Gaussian (forward)
+
+    def stage_row(stage, bound, ms, work, unit, per_unit, peak, peak_unit, note, measured_peak=None):
+        ach = work / (ms * 1e-3) / (1e12 if peak_unit in ("Tops/s", "TFLOP/s") else 1e9)
+        row = {"stage": stage, "bound": bound, "ms": round(ms, 4), "units": unit, "per_unit": per_unit,
+               "achieved": round(ach, 2), "peak": peak, "unit": peak_unit, "frac": round(ach / peak, 4),
+               "note": note}
+        if measured_peak:
+            row["frac_of_measured"] = round(ach / measured_peak, 4)
+        return row
+    stage_roofs = [
+        stage_row("query (render): cull + field query + aggregation", "hbm", st_render["query"],
+                  16.0 * n_all + per_g * n_vis, f"{n_all} Gaussians culled, {n_vis} queried", "16 B + 2148 B",
+                  HBM_PEAK_GBS, "GB/s", "line-granular hash gathers; see roofline_render.traffic", copy_gbs),
+        stage_row("project", "hbm", st_render["project"], 108.0 * n_vis * V, f"{n_vis * V} (view, Gaussian)",
+                  "108 B", HBM_PEAK_GBS, "GB/s", "", copy_gbs),
+        stage_row("bin + sort", "hbm", st_render["bin_sort"], (12.0 + 4 * 24.0) * st.n_entries + 8.0 * n_vis * V,
+                  f"{st.n_entries} tile entries", "12 B + 4 passes x 24 B per entry, 8 B per splat",
+                  HBM_PEAK_GBS, "GB/s", "per-entry bytes of a 4-pass 64-bit key sort; this build sorts splats "
+                  "by depth once and entries by a 16-bit key in 2 passes", copy_gbs),
+        stage_row("composite (render): blending + background", "alu", st_render["composite"], 20.0 * pairs,
+                  f"{pairs} (pixel, splat) pairs up to each pixel's last contributor", "20 VALU ops",
+                  round(VALU_PEAK_TOPS, 2), "Tops/s", "pairs counted to the last contributor only (a lower "
+                  "bound of the pairs walked); includes the background of the pixels that need one"),
+        stage_row("adjoint: Gaussian decoders", "mfma", st_serial["bwd_decoders"], 3 * mlp_fwd_flop * n_vis,
+                  f"{n_vis} Gaussians", f"{3 * mlp_fwd_flop / 1e3:.1f} kFLOP (forward recomputed, dX, dW)",
+                  MFMA_F32_PEAK, "TFLOP/s", "FP32 MFMA", measured["fp32_gemm_TFLOPs"]),
+        stage_row("adjoint: Gaussian hash tables", "atomics", st_serial["bwd_tables"], 2.0 * L_ * 8 * 2 * n_vis,
+                  f"{n_vis} Gaussians", f"{2 * L_ * 8 * 2} float additions", round(atomic_rate / 1e9, 1),
+                  "G float atomics/s (random, one per lane)",
+                  "float additions per second against the measured rate of uncombined random atomics: above 1 "
+                  "means the cell-run sums and line-combined issue beat one request per float"),
+    ]
+
     out = {"metric": METRIC, "value": round(1000.0 / ms_train, 3), "unit": "train steps/s (fwd+L1+bwd)",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_train, 4),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
@@ -394,7 +469,9 @@ def main():
                        "l1_dssim_hbm_frac": round(12.0 * V * 3 * H * W / (ms_loss_ds * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
            "tile_entries": st.n_entries,
            "roofline": roof,
-           "roofline_render": roof_fwd}
+           "roofline_render": roof_fwd,
+           "stage_rooflines": stage_roofs,
+           "measured_peaks": measured}
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams[0])

@@ -428,15 +428,23 @@ __device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
 }
 
 // Segmented inclusive sums of v over the runs that start at the set bits of
-// `heads`: the last lane of every run ends with the run's totals.
+// `heads`: the last lane of every run ends with the run's totals.  Only as
+// many doubling steps as the longest run needs are taken (steps with a
+// larger offset add nothing to any run's last lane, so the totals are the
+// same bit for bit): every run is at most 2^k lanes long exactly when each
+// lane has a head among itself and its 2^k - 1 predecessors.
 template <int N>
 __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
-  if (heads == ~0ull) return;   // every lane its own run
+  int steps = 0;
+  for (uint64_t cover = heads; cover != ~0ull && steps < 6; ++steps) cover |= cover << (1 << steps);
+  if (steps == 0) return;   // every lane its own run
   const int lane = lane_id();
   const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
   const int head = 63 - __clzll((long long)upto);
 #pragma unroll
-  for (int off = 1; off < 64; off <<= 1) {
+  for (int s = 0; s < 6; ++s) {
+    if (s >= steps) break;
+    const int off = 1 << s;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       const float t = __shfl_up(v[k], off, 64);
@@ -447,7 +455,11 @@ __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
 
 // Add the run totals of one level to a table-gradient level g ([T][2]):
 // the last lane of each run holds 16 floats, row[c] * 2 + f <- v[2c + f].
-// Every lane of the wave must call it.
+// Every lane of the wave must call it.  A staged cell occupies 16
+// consecutive words; its four 16-byte quarters are XOR-swizzled by the
+// cell's slot so that tail lanes of consecutive slots write different
+// banks.  The issue loop reads the slots linearly: every instruction still
+// covers whole cells.
 __device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t heads, const uint32_t (&row)[8],
                                               const float* v, CellStage& st) {
   const int lane = lane_id();
@@ -457,13 +469,14 @@ __device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t he
   const int K = __popcll(tails);
   for (int b = 0; b < K; b += STAGE_CELLS) {
     if (tail && rank >= b && rank < b + STAGE_CELLS) {
-      const int base = (rank - b) * 16;
+      const int cell = rank - b;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
-        st.idx[base + 2 * c] = row[c] * 2u;
-        st.idx[base + 2 * c + 1] = row[c] * 2u + 1u;
-        st.val[base + 2 * c] = v[2 * c];
-        st.val[base + 2 * c + 1] = v[2 * c + 1];
+        const int at = cell * 16 + 4 * ((c >> 1) ^ (cell & 3)) + 2 * (c & 1);
+        st.idx[at] = row[c] * 2u;
+        st.idx[at + 1] = row[c] * 2u + 1u;
+        st.val[at] = v[2 * c];
+        st.val[at + 1] = v[2 * c + 1];
       }
     }
     wave_lds_sync();
