@@ -728,6 +728,11 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         }
       }
       float dxc[D::SC];
+      // background rounds: the previous round's scatter (LDS staging in Xs,
+      // feature gradients in Ys) may still run on other waves up to here;
+      // the forward above needs no LDS staging, so the wait sits just
+      // before the adjoint's first staging write
+      if constexpr (RAY) __syncthreads();
       D::template bwd<true, D::SC, ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
       for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
@@ -798,7 +803,6 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       }
       __syncthreads();
       bg_round_scatter<Sh::L>(a, round * PPR, count, Ys, reinterpret_cast<CellStage*>(Xs)[w], w);
-      __syncthreads();
     }
   }
   write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
