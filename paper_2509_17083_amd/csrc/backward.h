@@ -92,7 +92,6 @@ struct GridBwdArgs {
   const void* table_rad;
   const float* dfeat_geo;
   const float* dfeat_rad;
-  bool pos_done;         // the decoder adjoint already added dL/dp through the weights
   float* g_pos;
   float* g_table_geo;
   float* g_table_rad;

@@ -13,10 +13,12 @@
 //                   part of the position gradient.  For background pixels
 //                   the radiance-table scatter-add follows in the same
 //                   kernel, round by round.
-//  k_grid_bwd       per Gaussian: hash-table scatter-add (cell runs summed,
-//                   lane-combined atomics) and, when the forward saved no
-//                   feature derivatives, the position gradient through the
-//                   interpolation weights and the contraction.
+//  k_grid_scatter   per Gaussian, when the forward saved the feature
+//                   derivatives: hash-table scatter-add (cell runs summed,
+//                   lane-combined atomics).
+//  k_grid_bwd       the same when no derivatives were saved, plus the
+//                   position gradient through the interpolation weights and
+//                   the contraction.
 //  k_dw_reduce      sums the per-workgroup dW partials in a fixed order.
 #include "backward.h"
 #include "block.h"
@@ -491,6 +493,26 @@ __device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t he
 
 
 
+// One level of one table for the whole wave: the 8 corner rows and trilinear
+// weights of each lane's cell, w_c * dL/df summed over cell runs, then the
+// staged scatter.  Every lane of the wave must call it.
+__device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t heads, const int (&ci)[3],
+                                              const float (&wv)[3], float2 df, bool dense, uint32_t side,
+                                              uint32_t mask, CellStage& st) {
+  uint32_t row[8];
+  float sv[16];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
+    const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
+    row[c] = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, dense, side, mask);
+    sv[2 * c] = wc * df.x;
+    sv[2 * c + 1] = wc * df.y;
+  }
+  run_sums<16>(heads, sv);
+  scatter_tails(g, heads, row, sv, st);
+}
+
 // Radiance-table scatter of one round of background pixels, inside the
 // background decoder adjoint (Sec. 3.3): the round's feature gradients sit
 // in LDS ([pixel][BG_DF_STRIDE], pixel-major), and the 8 waves split the
@@ -525,23 +547,9 @@ __device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, int firs
     int ci[3];
     float wv[3];
     grid_cell(x, res, ci, wv);
-    const uint32_t side = (uint32_t)res + 1u;
-    const bool drn = (a.grid.dense_rad >> lev) & 1u;
     const float2 df = *reinterpret_cast<const float2*>(sdf + pl * BG_DF_STRIDE + 2 * lev);
-    uint32_t row[8];
-    float sv[16];
-#pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int bx = c & 1, by = (c >> 1) & 1, bz = (c >> 2) & 1;
-      const float wc = ((bx ? wv[0] : 1.f - wv[0]) * (by ? wv[1] : 1.f - wv[1])) * (bz ? wv[2] : 1.f - wv[2]);
-      row[c] = corner_row((uint32_t)ci[0] + bx, (uint32_t)ci[1] + by, (uint32_t)ci[2] + bz, drn, side,
-                          a.grid.mask_rad);
-      sv[2 * c] = wc * df.x;
-      sv[2 * c + 1] = wc * df.y;
-    }
-    const uint64_t heads = cell_heads(ci);
-    run_sums<16>(heads, sv);
-    scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, row, sv, st);
+    scatter_level(a.g_table_rad + (size_t)lev * Tr * 2, cell_heads(ci), ci, wv, df, (a.grid.dense_rad >> lev) & 1u,
+                  (uint32_t)res + 1u, a.grid.mask_rad, st);
   }
 }
 
@@ -808,6 +816,50 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
   write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
+// Hash-table adjoint of the surviving Gaussians when the decoder adjoint has
+// already formed dL/dp from the saved feature derivatives: only the
+// scatter-add of w_c * dL/df into both tables remains.  One lane per
+// Gaussian, all levels per lane, one table at a time (fewer live registers,
+// more waves per SIMD to cover the atomics' issue).
+__global__ __launch_bounds__(256) void k_grid_scatter(GridBwdArgs a) {
+  __shared__ CellStage stage[4];
+  CellStage& st = stage[threadIdx.x / 64];
+  const int item = blockIdx.x * 256 + threadIdx.x;
+  const int count = *a.count;
+  if (blockIdx.x * 256 >= count) return;          // whole workgroup idle (uniform)
+  const bool valid = item < count;
+  const int gi = valid ? a.vis_idx[item] : 0;
+  double x[3];
+  contract_f64(a.grid, (double)a.pos[gi], (double)a.pos[a.n + gi], (double)a.pos[2 * a.n + gi], x);
+  const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
+  const bool single = a.grid.single != 0;
+  const bool do_geo = a.g_table_geo && !single;
+  for (int lev = 0; lev < a.grid.L; ++lev) {
+    const int res = a.grid.res[lev];
+    int ci[3];
+    float wv[3];
+    grid_cell(x, res, ci, wv);
+    const uint32_t side = (uint32_t)res + 1u;
+    float2 dg = make_float2(0.f, 0.f), dr = dg;
+    if (valid) {
+      dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
+      dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
+    }
+    if (single) {
+      // one field read by both decoders: its feature gradient is the sum
+      dr.x += dg.x;
+      dr.y += dg.y;
+    }
+    const uint64_t heads = cell_heads(ci);
+    if (do_geo)
+      scatter_level(a.g_table_geo + (size_t)lev * Tg * 2, heads, ci, wv, dg, (a.grid.dense_geo >> lev) & 1u, side,
+                    a.grid.mask_geo, st);
+    if (a.g_table_rad)
+      scatter_level(a.g_table_rad + (size_t)lev * Tr * 2, heads, ci, wv, dr, (a.grid.dense_rad >> lev) & 1u, side,
+                    a.grid.mask_rad, st);
+  }
+}
+
 // Hash-grid adjoint of the surviving Gaussians, one lane per Gaussian and all
 // levels per lane: scatter-add of w_c * dL/df into both tables (cell runs of
 // consecutive Gaussians summed first; they share cells at the coarse levels
@@ -825,7 +877,6 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   if (blockIdx.x * 256 >= count) return;          // whole workgroup idle (uniform)
   const bool valid = item < count;
   const int gi = valid ? a.vis_idx[item] : 0;
-  const bool pos_done = a.pos_done;   // dL/dp through the weights added by the decoder adjoint
   float pxf = 0.f, pyf = 0.f, pzf = 0.f;
   if (valid) {
     pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
@@ -864,8 +915,8 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
                      cz = (uint32_t)ci[2] + ((c >> 2) & 1);
       rg[c] = corner_row(cx, cy, cz, dgn, side, a.grid.mask_geo);
       rr[c] = corner_row(cx, cy, cz, drn, side, a.grid.mask_rad);
-      vg[c] = valid && !single && !pos_done ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
-      vr[c] = valid && !pos_done ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
+      vg[c] = valid && !single ? load_entry(table_geo, (size_t)lev * Tg + rg[c]) : make_float2(0.f, 0.f);
+      vr[c] = valid ? load_entry(table_rad, (size_t)lev * Tr + rr[c]) : make_float2(0.f, 0.f);
     }
     float sg[16], sr[16];
 #pragma unroll
@@ -894,7 +945,7 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
       scatter_tails(a.g_table_rad + (size_t)lev * Tr * 2, heads, rr, sr, st);
     }
   }
-  if (valid && a.g_pos && !pos_done) {
+  if (valid && a.g_pos) {
     float dp[3];
     contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
 #pragma unroll
@@ -964,11 +1015,14 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
     gb.table_rad = a.table_rad;
     gb.dfeat_geo = a.dfeat_geo;
     gb.dfeat_rad = a.dfeat_rad;
-    gb.pos_done = a.jac != nullptr;
     gb.g_pos = a.g_pos;
     gb.g_table_geo = a.g_table_geo;
     gb.g_table_rad = a.g_table_rad;
-    k_grid_bwd<TT><<<(unsigned)((a.n + 255) / 256 > 0 ? (a.n + 255) / 256 : 1), 256, 0, st>>>(gb);
+    const unsigned blocks = (unsigned)((a.n + 255) / 256 > 0 ? (a.n + 255) / 256 : 1);
+    if (a.jac)
+      k_grid_scatter<<<blocks, 256, 0, st>>>(gb);   // dL/dp already formed by the decoder adjoint
+    else
+      k_grid_bwd<TT><<<blocks, 256, 0, st>>>(gb);
   }
   // BWD_STAGE_BG_TABLES: the background decoder adjoint scatters its table
   // gradients itself; the stage launches nothing.
