@@ -53,11 +53,11 @@ def measured_traffic(kernel, field="traffic_bytes"):
 
 def cpu_baseline(scene, cam):
     """The FP64 oracle (as it stands) on a bounded sample of the same train
-    step: forward (field query + aggregation + projection of every 10th
-    Gaussian; blending + background of 64 random 16x16 tiles against that
-    thinned set), L1 loss on those pixels and the exact backward (autograd).
-    Scaled to a full frame: per-Gaussian work x10, blending x10 (pair
-    density) x tiles/64."""
+    step (about 10-20 s on 16 host threads): forward (field query +
+    aggregation + projection of every 2nd Gaussian; blending + background of
+    160 random 16x16 tiles against that thinned set), L1 loss on those pixels
+    and the exact backward (autograd).  Scaled to a full frame: per-Gaussian
+    work x2, blending x2 (pair density) x tiles/160."""
     import numpy as np
     import torch
 
@@ -65,7 +65,7 @@ def cpu_baseline(scene, cam):
     from oracle import hyrf_oracle as O
 
     torch.set_num_threads(os.cpu_count() or 1)
-    stride = 10
+    stride = 2
     params, fields = O.from_scene(scene)
     sel = torch.arange(0, params.pos.shape[0], stride)
 
@@ -77,7 +77,7 @@ def cpu_baseline(scene, cam):
         t.requires_grad_(True)
     rng = np.random.default_rng(0)
     tiles_x, tiles_y = (cam.width + 15) // 16, (cam.height + 15) // 16
-    pick = rng.choice(tiles_x * tiles_y, size=64, replace=False)
+    pick = rng.choice(tiles_x * tiles_y, size=160, replace=False)
     pix = []
     for t in pick:
         ty, tx = divmod(int(t), tiles_x)
@@ -114,7 +114,7 @@ def cpu_baseline(scene, cam):
     fwd_ms = (fg * stride + fp * scale_px) * 1e3
     return {"value": round(1000.0 / full_ms, 7), "unit": "train steps/s (fwd+L1+bwd)", "ms_per_step": round(full_ms, 1),
             "render_ms_per_frame": round(fwd_ms, 1), "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": f"FP64 oracle: every {stride}th Gaussian ({len(sel)}) through query+projection, "
+            "sample": f"FP64 oracle: one Gaussian in {stride} ({len(sel)}) through query+projection, "
                       f"{len(pick)} random 16x16 tiles through blending + background + L1, autograd backward; "
                       f"scaled x{stride} per Gaussian and x{stride}x{tiles_x * tiles_y}/{len(pick)} per pixel",
             "sample_seconds": round(t3 - t0, 2)}
