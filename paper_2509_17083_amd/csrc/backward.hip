@@ -127,17 +127,18 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
         }
       }
       if (__ballot(contrib)) {
-        gu = wave_sum_dpp(gu); gv = wave_sum_dpp(gv); ga = wave_sum_dpp(ga);
-        gb = wave_sum_dpp(gb); gc = wave_sum_dpp(gc); go = wave_sum_dpp(go);
-        gr = wave_sum_dpp(gr); gg = wave_sum_dpp(gg); gbb = wave_sum_dpp(gbb);
-        // the record's 9 floats from lanes 0..8 in one instruction: one or
-        // two 64-byte lines, so the atomics combine into one or two requests
+        // record fields 0..7 summed transposed (lane 2f holds field f),
+        // field 8 by a plain reduction
+        const float v8[8] = {gu, gv, ga, gb, gc, go, gr, gg};
+        const float t8 = wave_sum8_transposed(v8);
+        const float t9 = wave_sum_dpp(gbb);
+        // the record's 9 floats from 9 lanes of one instruction: one or two
+        // 64-byte lines, so the atomics combine into one or two requests
         const int ln = lane_id();
         const uint32_t id = sid[k];
-        if (ln < GS && id < a.n_rec) {
-          const float val = ln == 0 ? gu : ln == 1 ? gv : ln == 2 ? ga : ln == 3 ? gb : ln == 4 ? gc
-                          : ln == 5 ? go : ln == 6 ? gr : ln == 7 ? gg : gbb;
-          atomicAdd(a.gs + (size_t)id * GS + ln, val);
+        if (ln < 16 && ((ln & 1) == 0 || ln == 1) && id < a.n_rec) {
+          const int field = ln == 1 ? 8 : ln >> 1;
+          atomicAdd(a.gs + (size_t)id * GS + field, ln == 1 ? t9 : t8);
         }
       }
     }

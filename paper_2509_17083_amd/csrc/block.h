@@ -44,6 +44,39 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Totals of 8 per-lane values over the wave, transposed: lane l ends with
+// the total of value (l >> 1) & 7.  A butterfly over the lane bits inside
+// each 16-lane row halves the live values per step (partners l ^ 15, l ^ 7,
+// l ^ 3 by DPP row_mirror, row_half_mirror, quad_perm [3,2,1,0]; lanes keep
+// the upper half of their values when bit 3, 2, 1 is set), quad_perm
+// [1,0,3,2] adds the l ^ 1 partner, and two lane permutes add the other
+// rows.  26 lane operations for 8 sums instead of 8 full reductions.
+__device__ __forceinline__ float wave_sum8_transposed(const float (&v)[8]) {
+  const int lane = lane_id();
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0, b1 = (lane & 2) != 0;
+  float a[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const float lo = v[m] + dpp_mov<0x140, 0xf, true>(v[m]);          // row_mirror
+    const float hi = v[m + 4] + dpp_mov<0x140, 0xf, true>(v[m + 4]);
+    a[m] = b3 ? hi : lo;
+  }
+  float b[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const float lo = a[m] + dpp_mov<0x141, 0xf, true>(a[m]);          // row_half_mirror
+    const float hi = a[m + 2] + dpp_mov<0x141, 0xf, true>(a[m + 2]);
+    b[m] = b2 ? hi : lo;
+  }
+  const float lo = b[0] + dpp_mov<0x1B, 0xf, true>(b[0]);             // quad_perm [3,2,1,0]
+  const float hi = b[1] + dpp_mov<0x1B, 0xf, true>(b[1]);
+  float c = b1 ? hi : lo;
+  c += dpp_mov<0xB1, 0xf, true>(c);                                   // quad_perm [1,0,3,2]
+  c += __shfl_xor(c, 16, WAVE);
+  c += __shfl_xor(c, 32, WAVE);
+  return c;
+}
+
 // Exclusive prefix sum over a workgroup of NT threads (NT a multiple of 64,
 // at most 1024).  `sh` must hold NT/64 + 1 uint32.  Returns the exclusive
 // prefix of the calling thread; *total receives the workgroup sum.  Contains

@@ -142,10 +142,14 @@ def test_staged_backward_equals_one_call():
     qo.feat_jac = None                                                    # dL/dp with tables gathered again
     g5 = P.render_backward(ds, cams, dataclasses.replace(st, c=dict(st.c, qout=qo)), dL)
     torch.cuda.synchronize()
+    # float atomics add in arbitrary order: identical repeated calls already
+    # differ by up to ~1e-5 relative on position gradients that are small
+    # sums of larger terms (measured: 0.9 of rtol 1e-5 + 1e-7 max), so the
+    # floor is 1e-6 of the largest element
     for k, v in g1.items():
         if v is not None:
             for g in (g2, g3, g4, g5):
-                assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-7 * float(v.abs().max()) + 1e-12), k
+                assert torch.allclose(g[k], v, rtol=1e-5, atol=1e-6 * float(v.abs().max()) + 1e-12), k
 
 
 def test_gradient_matches_central_differences_along_random_directions():
