@@ -431,7 +431,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // Lanes whose cell differs from the previous lane's (lane 0 always).
 __device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
   const int lane = lane_id();
-  const int p0 = __shfl_up(ci[0], 1, 64), p1 = __shfl_up(ci[1], 1, 64), p2 = __shfl_up(ci[2], 1, 64);
+  const int p0 = wave_shr1(ci[0]), p1 = wave_shr1(ci[1]), p2 = wave_shr1(ci[2]);
   return __ballot(lane == 0 || p0 != ci[0] || p1 != ci[1] || p2 != ci[2]);
 }
 
@@ -455,7 +455,7 @@ __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
     const int off = 1 << s;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const float t = __shfl_up(v[k], off, 64);
+      const float t = off == 1 ? wave_shr1(v[k]) : __shfl_up(v[k], off, 64);
       if (lane - off >= head) v[k] += t;
     }
   }

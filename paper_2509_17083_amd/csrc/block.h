@@ -44,6 +44,11 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
+// Lane i receives lane i - 1's value, lane 0 receives 0 (DPP wave_shr:1: a
+// VALU move, no LDS crossbar).  Every lane of the wave must be active.
+__device__ __forceinline__ int wave_shr1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ float wave_shr1(float x) { return __int_as_float(wave_shr1(__float_as_int(x))); }
+
 // Totals of 8 per-lane values over the wave, transposed: lane l ends with
 // the total of value (l >> 1) & 7.  A butterfly over the lane bits inside
 // each 16-lane row halves the live values per step (partners l ^ 15, l ^ 7,
