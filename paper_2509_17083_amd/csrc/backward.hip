@@ -582,28 +582,20 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
 // background decoder adjoint (Sec. 3.3): the round's feature gradients sit
 // in LDS ([pixel][BG_DF_STRIDE], pixel-major), and the 8 waves split the
 // work as 2 halves of 64 consecutive pixels x 4 level groups (levels
-// lg, lg + 4, ...).  Each lane recomputes its pixel's contracted sphere
-// point in float64, so the cells match the forward gather exactly.  The
-// atomics do not return: they drain while the next round's MFMA work runs.
+// lg, lg + 4, ...).  The pixels' contracted sphere points (float64, the
+// same cells as the forward gather) come from LDS too.  The atomics do not
+// return: they drain while the next round's MFMA work runs.
 constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
 
 template <int L, bool MERGE>
-__device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, int first, int count, const float* sdf,
+__device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, const float* sdf, const double* sx,
                                                  CellStage& st, int w) {
   static_assert(2 * L + 2 <= BG_DF_STRIDE, "LDS row too short");
   const int lane = lane_id();
   const int pl = (w & 1) * 64 + lane;
   const int lg = w >> 1;
-  const int item = first + pl;
-  const bool valid = item < count;
-  const int pix = valid ? item : 0;
-  const int HW = a.W * a.H;
-  const int v = pix / HW;
-  const int rem = pix - v * HW;
-  const int yy = rem / a.W, xx = rem - yy * a.W;
-  double ps[3], d[3], x[3];
-  sphere_point_f64(a.cams.c[v], xx, yy, (double)a.grid.bg_radius, ps, d);
-  contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+  // the pixel's contracted sphere point, computed once by the decoder phase
+  const double x[3] = {sx[3 * pl], sx[3 * pl + 1], sx[3 * pl + 2]};
   const uint32_t Tr = a.grid.mask_rad + 1u;
 #pragma unroll 1
   for (int k = 0; k < L / 4; ++k) {
@@ -640,8 +632,11 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
   // loop: every MFMA A operand is then an LDS read, not an L2 round trip
   __shared__ __attribute__((aligned(16))) float s_wf_col[Sh::W_COL];
   __shared__ __attribute__((aligned(16))) float s_wb_col[B::WB_COL];
-  // the geometry decoder's too, for the Gaussians
-  __shared__ __attribute__((aligned(16))) float s_wf_geo[RAY ? 4 : Sh::W_GEO];
+  // the geometry decoder's too, for the Gaussians; for background pixels
+  // the same space holds the round's contracted sphere points (float64,
+  // two buffers by round parity: a wave may still scatter round r while
+  // another starts round r + 1)
+  __shared__ __attribute__((aligned(16))) float s_wf_geo[RAY ? 2 * PPR * 3 * 2 : Sh::W_GEO];
   __shared__ __attribute__((aligned(16))) float s_wb_geo[RAY ? 4 : B::WB_GEO];
   {
     const float4* src_f = reinterpret_cast<const float4*>(a.wf_col);
@@ -743,6 +738,14 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       const int yy = rem / a.W, xx = rem - yy * a.W;
       double ps[3], d[3];
       sphere_point_f64(a.cams.c[v_r], xx, yy, (double)a.grid.bg_radius, ps, d);
+      contract_f64(a.grid, ps[0], ps[1], ps[2], x);
+      if (g == 0 && a.g_table_rad) {
+        double* sx = reinterpret_cast<double*>(s_wf_geo) + (round & 1) * PPR * 3;
+        const int pl = w * 16 + j;
+        sx[3 * pl] = x[0];
+        sx[3 * pl + 1] = x[1];
+        sx[3 * pl + 2] = x[2];
+      }
       if (a.bg_feat) {
         // features saved by the forward
 #pragma unroll
@@ -752,7 +755,6 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
           fr[2 * k + 1] = f2.y;
         }
       } else {
-        contract_f64(a.grid, ps[0], ps[1], ps[2], x);
         gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, (const TT*)a.table_rad, fg, fr, nullptr, nullptr);
       }
       const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
@@ -877,7 +879,8 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       __syncthreads();
       // shared-corner merging where the round's decoder work is short enough
       // (bfloat16 operands) that the scatter's requests bound the kernel
-      bg_round_scatter<Sh::L, BF>(a, round * PPR, count, Ys, reinterpret_cast<CellStage*>(Xs)[w], w);
+      bg_round_scatter<Sh::L, BF>(a, Ys, reinterpret_cast<const double*>(s_wf_geo) + (round & 1) * PPR * 3,
+                                  reinterpret_cast<CellStage*>(Xs)[w], w);
     }
   }
   write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
