@@ -2,7 +2,9 @@
 // reduce-then-scan per pass (no inter-workgroup waiting):
 //   1. per-workgroup digit histogram -> hist[digit * nblocks + block]
 //   2. exclusive scan of hist (digit-major) -> global base of (digit, block)
-//   3. per-workgroup stable ranking and scatter.
+//   3. per-workgroup stable ranking, reorder by digit in LDS, then a write
+//      in LDS order: consecutive lanes store consecutive addresses of one
+//      digit's run (coalesced), instead of 64 scattered 4-byte stores.
 // Each workgroup owns SORT_ITEMS consecutive pairs; wave w owns the w-th
 // quarter and walks it in 64-item rounds, so the rank of an item among equal
 // digits follows input order (stability).
@@ -39,7 +41,11 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
                                                       uint32_t* __restrict__ vout, int64_t n,
                                                       int shift, const uint32_t* __restrict__ hist,
                                                       int nblocks) {
+  static_assert(NT == RADIX, "one thread per digit");
   __shared__ uint32_t cnt[NW][RADIX];
+  __shared__ uint32_t sk[SORT_ITEMS], sv[SORT_ITEMS];   // the workgroup's pairs, ordered by digit
+  __shared__ uint32_t lstart[RADIX], gbase[RADIX];
+  __shared__ uint32_t scan_sh[NW + 1];
   const int lane = lane_id();
   const int w = threadIdx.x / WAVE;
   for (int k = threadIdx.x; k < NW * RADIX; k += NT) (&cnt[0][0])[k] = 0;
@@ -70,16 +76,20 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     if (ok && leader) cnt[w][d] = before + (uint32_t)__popcll(m);
   }
   __syncthreads();
-  // per digit: prefix over waves + global base of (digit, block)
+  // per digit: prefix over waves, the digit's start in the workgroup's
+  // digit order, and the global base of (digit, block)
   {
     const int d = threadIdx.x;
-    uint32_t run = hist[(int64_t)d * nblocks + blockIdx.x];
+    uint32_t tot = 0;
 #pragma unroll
     for (int ww = 0; ww < NW; ++ww) {
-      uint32_t c = cnt[ww][d];
-      cnt[ww][d] = run;
-      run += c;
+      const uint32_t c = cnt[ww][d];
+      cnt[ww][d] = tot;
+      tot += c;
     }
+    uint32_t all;
+    lstart[d] = block_excl_scan<NT>(tot, scan_sh, &all);
+    gbase[d] = hist[(int64_t)d * nblocks + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -87,10 +97,20 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     const int64_t i = chunk + (int64_t)r * WAVE + lane;
     if (i < n) {
       const uint32_t d = (key[r] >> shift) & 0xFFu;
-      const uint32_t pos = cnt[w][d] + rank[r];
-      kout[pos] = key[r];
-      vout[pos] = val[r];
+      const uint32_t lp = lstart[d] + cnt[w][d] + rank[r];
+      sk[lp] = key[r];
+      sv[lp] = val[r];
     }
+  }
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+  const int m = (int)min((int64_t)SORT_ITEMS, n - base);
+  for (int t = threadIdx.x; t < m; t += NT) {
+    const uint32_t k = sk[t];
+    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t pos = gbase[d] + ((uint32_t)t - lstart[d]);
+    kout[pos] = k;
+    vout[pos] = sv[t];
   }
 }
 }  // namespace
