@@ -46,27 +46,59 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint32_t* __restrict_
   cnt[i] = c;
 }
 
-// write the entries of each splat in depth order: key = view*tiles + tile
+// write the entries of each splat in depth order: key = view*tiles + tile.
+// A wave expands the entries of its 64 consecutive splats together: their
+// exclusive offsets are consecutive, so lane e of each step writes entry
+// first + e, found by a binary search over the wave's offsets (coalesced
+// stores, large splats spread over all lanes).
 __global__ __launch_bounds__(256) void k_dup(const uint32_t* __restrict__ skey,
                                              const uint32_t* __restrict__ sval,
                                              const int4* __restrict__ rect,
                                              const uint32_t* __restrict__ off, int64_t m, int n_max,
                                              int tiles_x, int tiles, int64_t capacity,
                                              uint32_t* __restrict__ ekey, uint32_t* __restrict__ eval) {
+  __shared__ uint32_t s_off[4][WAVE];
+  __shared__ int4 s_rect[4][WAVE];
+  __shared__ uint32_t s_id[4][WAVE];
+  const int lane = lane_id();
+  const int w = threadIdx.x / WAVE;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= m || skey[i] == 0xFFFFFFFFu) return;
-  const uint32_t id = sval[i];
-  const int4 r = rect[id];
-  const uint32_t vbase = (id / (uint32_t)n_max) * (uint32_t)tiles;
-  uint64_t o = off[i];
-  for (int ty = r.y; ty < r.w; ++ty)
-    for (int tx = r.x; tx < r.z; ++tx) {
-      if ((int64_t)o < capacity) {
-        ekey[o] = vbase + (uint32_t)(ty * tiles_x + tx);
-        eval[o] = id;
-      }
-      ++o;
+  const int64_t i0 = i - lane;                    // the wave's first splat
+  if (i0 >= m) return;                            // whole wave idle (uniform)
+  const bool ok = i < m && skey[i] != 0xFFFFFFFFu;
+  const uint32_t id = ok ? sval[i] : 0u;
+  const int4 r = ok ? rect[id] : make_int4(0, 0, 0, 0);
+  const uint32_t cnt = ok ? (uint32_t)((r.z - r.x) * (r.w - r.y)) : 0u;
+  const uint32_t first = off[i0];
+  const uint32_t rel = i < m ? off[i] - first : 0u;
+  // entries of the wave: the end of its last in-range splat (offsets plus
+  // counts do not decrease along the array)
+  const int last = (int)min((int64_t)WAVE - 1, m - 1 - i0);
+  const uint32_t total = __shfl(rel + cnt, last, WAVE);
+  // lanes past the array sit at the end, so the offsets stay sorted
+  s_off[w][lane] = i < m ? rel : total;
+  s_rect[w][lane] = r;
+  s_id[w][lane] = id;
+  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  __builtin_amdgcn_wave_barrier();
+  for (uint32_t e = lane; e < total; e += WAVE) {
+    // the splat j with s_off[j] <= e < s_off[j + 1] (empty splats skipped)
+    int lo = 0, hi = WAVE - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_off[w][mid] <= e) lo = mid; else hi = mid - 1;
     }
+    const int4 rr = s_rect[w][lo];
+    const uint32_t k = e - s_off[w][lo];
+    const int wdt = rr.z - rr.x;
+    const int ty = rr.y + (int)(k / (uint32_t)wdt), tx = rr.x + (int)(k % (uint32_t)wdt);
+    const uint32_t sid = s_id[w][lo];
+    const int64_t o = (int64_t)first + e;
+    if (o < capacity) {
+      ekey[o] = (sid / (uint32_t)n_max) * (uint32_t)tiles + (uint32_t)(ty * tiles_x + tx);
+      eval[o] = sid;
+    }
+  }
 }
 
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key, int64_t ne,
