@@ -107,6 +107,13 @@ typedef struct {
    * log2_T_geo and qparams_geo are ignored, and the whole table gradient goes
    * to hyrf_grads.table_rad (hyrf_grads.table_geo is ignored). */
   int32_t single_field;
+  /* Adjoint only; no effect on any result beyond float rounding.  How the
+   * background points' radiance-table scatter treats corners shared by
+   * consecutive grid cells: 0 = automatic (merged into one cell before the
+   * atomics with bfloat16 decoders, where the atomic requests bound the
+   * scatter; not with float32 decoders), 1 = always merged, 2 = never.
+   * Other values: HYRF_ERR_INVALID_ARGUMENT. */
+  int32_t scatter_merge;
 } hyrf_fields;
 
 /* Pinhole camera, world -> camera p_c = R p + t (Sec. 3.3 Eq. 8), OpenCV axes

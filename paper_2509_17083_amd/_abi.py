@@ -31,7 +31,8 @@ class hyrf_fields(C.Structure):
                 ("hidden", C.c_int32), ("n_hidden", C.c_int32), ("mlp_dtype", C.c_int32),
                 ("mlp_geo", P), ("mlp_col", P), ("aabb_center", C.c_float * 3),
                 ("aabb_inv_half", C.c_float * 3), ("bg_radius", C.c_float), ("tau_T", C.c_float),
-                ("qparams_geo", P), ("qparams_rad", P), ("single_field", C.c_int32)]
+                ("qparams_geo", P), ("qparams_rad", P), ("single_field", C.c_int32),
+                ("scatter_merge", C.c_int32)]
 
 
 class hyrf_camera(C.Structure):

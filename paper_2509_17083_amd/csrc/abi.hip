@@ -95,6 +95,7 @@ hyrf_status check_fields(const hyrf_fields* f) {
   REQ(f->n_hidden == 1 || f->n_hidden == 2, "n_hidden must be 1 or 2");
   REQ(f->bg_radius > 0.f, "bg_radius must be positive");
   for (int d = 0; d < 3; ++d) REQ(f->aabb_inv_half[d] > 0.f, "aabb_inv_half must be positive");
+  REQ(f->scatter_merge >= 0 && f->scatter_merge <= 2, "scatter_merge = %d must be 0, 1 or 2", f->scatter_merge);
   if (!(f->table_dtype == HYRF_F32 || f->table_dtype == HYRF_F16 || f->table_dtype == HYRF_U8))
     return fail(HYRF_ERR_UNSUPPORTED, "table dtype %d not supported (F32, F16 or U8)", f->table_dtype);
   REQ(f->table_dtype != HYRF_U8 || ((f->single_field || f->qparams_geo) && f->qparams_rad),
@@ -518,6 +519,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.feat_geo = q->feat_geo;
   F.feat_rad = q->feat_rad;
   F.jac = q->feat_jac;
+  F.merge = fields->scatter_merge == 1 ? 1 : fields->scatter_merge == 2 ? 0 : (fields->mlp_dtype == HYRF_BF16 ? 1 : 0);
   F.dgeo = w.dgeo;
   F.dcol = w.dcol;
   F.dfeat_geo = w.dfeat_geo;

@@ -80,6 +80,7 @@ struct FieldBwdArgs {
   const float* dL;
   const float* bg_feat;  // [V*H*W][2L] saved background features, or NULL (gather)
   const float* jac;      // [n][L][12] saved feature derivatives, or NULL
+  int merge;             // background scatter: merge corners shared by consecutive cells
 };
 
 struct GridBwdArgs {

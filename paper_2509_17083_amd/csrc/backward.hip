@@ -877,10 +877,14 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
             valid ? make_float2(dfr[2 * k], dfr[2 * k + 1]) : make_float2(0.f, 0.f);
       }
       __syncthreads();
-      // shared-corner merging where the round's decoder work is short enough
-      // (bfloat16 operands) that the scatter's requests bound the kernel
-      bg_round_scatter<Sh::L, BF>(a, Ys, reinterpret_cast<const double*>(s_wf_geo) + (round & 1) * PPR * 3,
-                                  reinterpret_cast<CellStage*>(Xs)[w], w);
+      // shared-corner merging (by default where the round's decoder work is
+      // short enough, bfloat16 operands, that the scatter's requests bound
+      // the kernel); the choice is uniform over the launch
+      const double* sx = reinterpret_cast<const double*>(s_wf_geo) + (round & 1) * PPR * 3;
+      if (a.merge)
+        bg_round_scatter<Sh::L, true>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
+      else
+        bg_round_scatter<Sh::L, false>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
     }
   }
   write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);

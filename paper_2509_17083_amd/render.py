@@ -53,6 +53,7 @@ class DeviceScene:
     qparams_geo: Optional[torch.Tensor] = None   # (L, 2) (min, step) for U8 tables
     qparams_rad: Optional[torch.Tensor] = None
     single_field: int = 0    # one field (the radiance table) feeds both decoders
+    scatter_merge: int = 0   # background table scatter: 0 automatic, 1 merge shared corners, 2 never
 
     @property
     def n(self) -> int:
@@ -149,6 +150,7 @@ class DeviceScene:
         if self.table_dtype == U8:
             f.qparams_geo, f.qparams_rad = self.qparams_geo.data_ptr(), self.qparams_rad.data_ptr()
         f.single_field = int(self.single_field)
+        f.scatter_merge = int(self.scatter_merge)
         return f
 
     def c_gauss(self) -> A.hyrf_gaussians:

@@ -72,6 +72,7 @@ def _query(A, lib, f, cams=None, n_views=1, out=True, ws_bytes=1 << 20):
 @pytest.mark.parametrize("kw,status", [
     (dict(levels=5), 1), (dict(features=4), 1), (dict(log2_T_rad=30), 1), (dict(hidden=100), 1),
     (dict(n_hidden=3), 1), (dict(table_dtype=7), 2), (dict(levels=12), 2), (dict(bg_radius=0.0), 1),
+    (dict(scatter_merge=3), 1), (dict(scatter_merge=-1), 1),
 ])
 def test_query_rejects_bad_fields(kw, status):
     A, lib = _lib()
