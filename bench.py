@@ -138,8 +138,8 @@ def main():
                          "once before timing) or the generator's seeded order")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the render step of this "
-              f"build is a single-GPU kernel path; multi-GPU sharding is described, not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the render step is a "
+              f"single-GPU kernel path; multi-GPU sharding is described, not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -436,7 +436,7 @@ def main():
                   "108 B", HBM_PEAK_GBS, "GB/s", "", copy_gbs),
         stage_row("bin + sort", "hbm", st_render["bin_sort"], (12.0 + 4 * 24.0) * st.n_entries + 8.0 * n_vis * V,
                   f"{st.n_entries} tile entries", "12 B + 4 passes x 24 B per entry, 8 B per splat",
-                  HBM_PEAK_GBS, "GB/s", "per-entry bytes of a 4-pass 64-bit key sort; this build sorts splats "
+                  HBM_PEAK_GBS, "GB/s", "per-entry bytes of a 4-pass 64-bit key sort; the library sorts splats "
                   "by depth once and entries by a 16-bit key in 2 passes", copy_gbs),
         stage_row("composite (render): blending + background", "alu", st_render["composite"], 20.0 * pairs,
                   f"{pairs} (pixel, splat) pairs up to each pixel's last contributor", "20 VALU ops",
