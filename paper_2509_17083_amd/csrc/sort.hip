@@ -1,8 +1,11 @@
 // Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
-// reduce-then-scan per pass (no inter-workgroup waiting):
+// reduce-then-scan per pass (no inter-workgroup waiting), three launches:
 //   1. per-workgroup digit histogram -> hist[digit * nblocks + block]
-//   2. exclusive scan of hist (digit-major) -> global base of (digit, block)
-//   3. per-workgroup stable ranking, reorder by digit in LDS, then a write
+//   2. one workgroup per digit: exclusive scan of the digit's row of hist
+//      over the workgroups, in place, and the row's total -> tot[digit]
+//   3. per workgroup: global base of (digit, block) = exclusive sum of the
+//      totals of the smaller digits + the scanned hist entry; stable
+//      ranking, reorder by digit in LDS, then a write
 //      in LDS order: consecutive lanes store consecutive addresses of one
 //      digit's run (coalesced), instead of 64 scattered 4-byte stores.
 // Each workgroup owns SORT_ITEMS consecutive pairs; wave w owns the w-th
@@ -35,12 +38,41 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ 
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
+// Workgroup d: hist[d * nblocks + b] <- number of keys with digit d in the
+// workgroups below b; tot[d] <- number of keys with digit d.
+constexpr int OFF_PER = 4;   // consecutive row entries per thread and chunk
+__global__ __launch_bounds__(NT) void k_radix_offsets(uint32_t* __restrict__ hist,
+                                                      uint32_t* __restrict__ tot, int nblocks) {
+  __shared__ uint32_t sh[NW + 1];
+  const int d = blockIdx.x;
+  uint32_t carry = 0;
+  uint32_t* row = hist + (int64_t)d * nblocks;
+  for (int c0 = 0; c0 < nblocks; c0 += NT * OFF_PER) {   // uniform trip count: barriers inside
+    const int i0 = c0 + (int)threadIdx.x * OFF_PER;
+    uint32_t v[OFF_PER], s = 0;
+#pragma unroll
+    for (int q = 0; q < OFF_PER; ++q) {
+      v[q] = i0 + q < nblocks ? row[i0 + q] : 0u;
+      s += v[q];
+    }
+    uint32_t chunk;
+    uint32_t run = carry + block_excl_scan<NT>(s, sh, &chunk);
+#pragma unroll
+    for (int q = 0; q < OFF_PER; ++q) {
+      if (i0 + q < nblocks) row[i0 + q] = run;
+      run += v[q];
+    }
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) tot[d] = carry;
+}
+
 __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int64_t n,
                                                       int shift, const uint32_t* __restrict__ hist,
-                                                      int nblocks) {
+                                                      const uint32_t* __restrict__ dtot, int nblocks) {
   static_assert(NT == RADIX, "one thread per digit");
   __shared__ uint32_t cnt[NW][RADIX];
   __shared__ uint32_t sk[SORT_ITEMS], sv[SORT_ITEMS];   // the workgroup's pairs, ordered by digit
@@ -89,7 +121,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     }
     uint32_t all;
     lstart[d] = block_excl_scan<NT>(tot, scan_sh, &all);
-    gbase[d] = hist[(int64_t)d * nblocks + blockIdx.x];
+    gbase[d] = block_excl_scan<NT>(dtot[d], scan_sh, &all) + hist[(int64_t)d * nblocks + blockIdx.x];
   }
   __syncthreads();
 #pragma unroll
@@ -118,20 +150,22 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
 size_t radix_temp_elems(int64_t n) {
   int64_t nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
   if (nb < 1) nb = 1;
-  return (size_t)nb * RADIX + scan_temp_elems(nb * RADIX);
+  return (size_t)nb * RADIX + RADIX;
 }
 
 int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
                      uint32_t* temp, hipStream_t st) {
   if (n <= 1 || bits <= 0) return start;
+  if (bits > 32) bits = 32;
   const int nb = (int)((n + SORT_ITEMS - 1) / SORT_ITEMS);
+  const int passes = (bits + 7) / 8;
   uint32_t* hist = temp;
-  uint32_t* stemp = temp + (size_t)nb * RADIX;
+  uint32_t* tot = temp + (size_t)nb * RADIX;   // [RADIX] digit totals of the pass
   int cur = start;
-  for (int shift = 0; shift < bits; shift += 8) {
-    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, shift, hist, nb);
-    scan_exclusive_u32(hist, hist, (int64_t)nb * RADIX, stemp, nullptr, st);
-    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, hist, nb);
+  for (int p = 0; p < passes; ++p) {
+    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, 8 * p, hist, nb);
+    k_radix_offsets<<<RADIX, NT, 0, st>>>(hist, tot, nb);
+    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, 8 * p, hist, tot, nb);
     cur ^= 1;
   }
   return cur;

@@ -135,6 +135,46 @@ def test_bin_sort_bit_exact(V, n, W, H, seed):
     assert np.array_equal(ranges.cpu().numpy().astype(np.int64), ranges_o.numpy())
 
 
+def test_bin_sort_large_order_by_definition():
+    """4.5M splats (85% with an empty rectangle) and ~7M tile entries: both
+    radix sorts run more than 1024 workgroups, so each digit's offsets are
+    scanned over several chunks.  The oracle's per-entry loops are too slow
+    at this size; the result is checked against the order's definition
+    (entries by view, tile, depth, splat index), built here with numpy's
+    lexsort, bit for bit."""
+    P = _P()
+    from paper_2509_17083_amd import _abi as A
+    V, n, W, H = 1, 4_500_000, 1920, 1080
+    depth, rect, tw, th = hi.make_splat_records(V, n, W, H, seed=21)
+    empty = np.random.Generator(np.random.PCG64(22)).uniform(size=(V, n)) < 0.85
+    rect[..., 2] = np.where(empty, rect[..., 0], rect[..., 2])
+    r = rect.reshape(-1, 4).astype(np.int64)
+    w, h = r[:, 2] - r[:, 0], r[:, 3] - r[:, 1]
+    cnt = np.where((w > 0) & (h > 0), w * h, 0)
+    sid = np.repeat(np.arange(V * n, dtype=np.int64), cnt)
+    j = np.arange(sid.size, dtype=np.int64) - np.repeat(np.cumsum(cnt) - cnt, cnt)
+    tile = (r[sid, 1] + j // w[sid]) * tw + (r[sid, 0] + j % w[sid])
+    key = (sid // n) * (tw * th) + tile
+    order = np.lexsort((sid, depth.reshape(-1)[sid], key))
+    keys_e, ids_e = key[order], sid[order]
+    ne = int(keys_e.size)
+    k = np.arange(V * tw * th)
+    lo, hi_ = np.searchsorted(keys_e, k, "left"), np.searchsorted(keys_e, k, "right")
+    ranges_e = np.stack([np.where(hi_ > lo, lo, 0), np.where(hi_ > lo, hi_, 0)], axis=1)
+    _say("large bin/sort:", V * n, "splats,", ne, "entries")
+
+    count = torch.tensor([n], dtype=torch.int32, device="cuda")
+    d_rect = torch.from_numpy(rect).cuda()
+    d_depth = torch.from_numpy(depth).cuda()
+    spc = A.hyrf_splats(n, count.data_ptr(), None, d_rect.data_ptr(), d_depth.data_ptr(), None)
+    cams = [hi.look_at((0, -3, 0), (0, 0, 0), 100.0, W, H)] * V
+    keys, vals, ranges = P.bin_sort(cams, spc, n, ne, want_keys=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(keys[:ne].cpu().numpy().astype(np.int64), keys_e)
+    assert np.array_equal(vals[:ne].cpu().numpy().astype(np.int64), ids_e)
+    assert np.array_equal(ranges.cpu().numpy().astype(np.int64), ranges_e)
+
+
 def test_bin_sort_capacity_error():
     P = _P()
     from paper_2509_17083_amd import _abi as A
