@@ -155,8 +155,14 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
 }
 
 // ---------------------------------------------------------------- background
+// Background query: 4 waves per workgroup, 3 workgroups per CU (at most 168
+// registers per lane, 3 waves per SIMD).
+constexpr int BG_NT = 256;
+constexpr int BG_WAVES_PER_SIMD = 3;
+constexpr int BG_MAX_BLOCKS = 768;
+
 template <class Sh, class TT, bool BF>
-__global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
+__global__ __launch_bounds__(BG_NT, BG_WAVES_PER_SIMD) void k_bg_query(BgArgs a) {
   using M = MlpLds<Sh, BF>;
   __shared__ __attribute__((aligned(16))) typename M::T w_col[M::COL];
   M::load(w_col, a.w_col, true);
@@ -167,8 +173,8 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_bg_query(BgArgs a) {
   const int HW = a.W * a.H;
   const int count = a.list_count ? *a.list_count : a.cams.V * HW;
   const int groups = (count + 15) >> 4;
-  const int wave_g = blockIdx.x * (QUERY_NT / 64) + threadIdx.x / 64;
-  const int wave_n = gridDim.x * (QUERY_NT / 64);
+  const int wave_g = blockIdx.x * (BG_NT / 64) + threadIdx.x / 64;
+  const int wave_n = gridDim.x * (BG_NT / 64);
   const double radius = (double)a.grid.bg_radius;
   for (int grp = wave_g; grp < groups; grp += wave_n) {
     const int item = grp * 16 + j;
@@ -224,10 +230,10 @@ static void launch_query_t(const QueryArgs& a, int n_cap, hipStream_t st) {
 template <class Sh, class TT, bool BF>
 static void launch_bg_t(const BgArgs& a, int n_cap, hipStream_t st) {
   int groups = (n_cap + 15) / 16;
-  int blocks = (groups + QUERY_NT / 64 - 1) / (QUERY_NT / 64);
-  if (blocks > QUERY_MAX_BLOCKS) blocks = QUERY_MAX_BLOCKS;
+  int blocks = (groups + BG_NT / 64 - 1) / (BG_NT / 64);
+  if (blocks > BG_MAX_BLOCKS) blocks = BG_MAX_BLOCKS;
   if (blocks < 1) blocks = 1;
-  k_bg_query<Sh, TT, BF><<<blocks, QUERY_NT, 0, st>>>(a);
+  k_bg_query<Sh, TT, BF><<<blocks, BG_NT, 0, st>>>(a);
 }
 
 bool shape_supported(int L, int hid, int nh) {
