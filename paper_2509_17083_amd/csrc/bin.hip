@@ -101,14 +101,34 @@ __global__ __launch_bounds__(256) void k_dup(const uint32_t* __restrict__ skey,
   }
 }
 
+// Per-key [first, last) of the sorted keys: entry e opens its key's range
+// where key[e - 1] differs and closes it where key[e + 1] differs.  Each
+// thread takes RANGE_PER consecutive entries (one 16-byte load when the
+// group is whole and the keys are 16-byte aligned) and their two outer
+// neighbours.
+constexpr int RANGE_PER = 4;
 __global__ __launch_bounds__(256) void k_ranges(const uint32_t* __restrict__ key, int64_t ne,
                                                 uint32_t nkeys, uint32_t* __restrict__ ranges) {
-  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e >= ne) return;
-  const uint32_t k = key[e];
-  if (k >= nkeys) return;   // only reachable when n_entries disagrees with the device total
-  if (e == 0 || key[e - 1] != k) ranges[2 * (size_t)k] = (uint32_t)e;
-  if (e == ne - 1 || key[e + 1] != k) ranges[2 * (size_t)k + 1] = (uint32_t)(e + 1);
+  const int64_t e0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * RANGE_PER;
+  if (e0 >= ne) return;
+  uint32_t k[RANGE_PER + 2];   // key[e0 - 1 .. e0 + RANGE_PER]; out-of-range neighbours differ
+  if (e0 + RANGE_PER <= ne && ((uintptr_t)key & 15) == 0) {
+    const uint4 q = *reinterpret_cast<const uint4*>(key + e0);
+    k[1] = q.x; k[2] = q.y; k[3] = q.z; k[4] = q.w;
+  } else {
+#pragma unroll
+    for (int j = 0; j < RANGE_PER; ++j) k[1 + j] = e0 + j < ne ? key[e0 + j] : 0xFFFFFFFFu;
+  }
+  k[0] = e0 > 0 ? key[e0 - 1] : ~k[1];
+  k[RANGE_PER + 1] = e0 + RANGE_PER < ne ? key[e0 + RANGE_PER] : ~k[RANGE_PER];
+#pragma unroll
+  for (int j = 0; j < RANGE_PER; ++j) {
+    const int64_t e = e0 + j;
+    const uint32_t kk = k[1 + j];
+    if (e >= ne || kk >= nkeys) continue;   // kk >= nkeys: n_entries disagrees with the device total
+    if (k[j] != kk) ranges[2 * (size_t)kk] = (uint32_t)e;
+    if (e == ne - 1 || k[2 + j] != kk) ranges[2 * (size_t)kk + 1] = (uint32_t)(e + 1);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_zero_words(uint32_t* p, int64_t n) {
@@ -168,7 +188,8 @@ void launch_bin_sort(const BinArgs& a, const BinWs& w, hipStream_t st) {
   // 4. per-tile ranges
   k_zero_words<<<nblk(nranges), 256, 0, st>>>(a.ranges, nranges);
   if (a.n_entries > 0)
-    k_ranges<<<nblk(a.n_entries), 256, 0, st>>>(K[ecur], a.n_entries, (uint32_t)(a.V * tiles), a.ranges);
+    k_ranges<<<nblk((a.n_entries + RANGE_PER - 1) / RANGE_PER), 256, 0, st>>>(K[ecur], a.n_entries,
+                                                                           (uint32_t)(a.V * tiles), a.ranges);
 }
 
 }  // namespace hyrf

@@ -29,11 +29,15 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ 
   h[threadIdx.x] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
-#pragma unroll 4
+  uint32_t d[ROUNDS];   // all loads in flight before the first LDS update
+#pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
-    int64_t i = base + (int64_t)r * NT + threadIdx.x;
-    if (i < n) atomicAdd(&h[(keys[i] >> shift) & 0xFFu], 1u);
+    const int64_t i = base + (int64_t)r * NT + threadIdx.x;
+    d[r] = i < n ? (keys[i] >> shift) & 0xFFu : RADIX;
   }
+#pragma unroll
+  for (int r = 0; r < ROUNDS; ++r)
+    if (d[r] < RADIX) atomicAdd(&h[d[r]], 1u);
   __syncthreads();
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
