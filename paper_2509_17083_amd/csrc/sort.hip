@@ -5,9 +5,9 @@
 //      over the workgroups, in place, and the row's total -> tot[digit]
 //   3. per workgroup: global base of (digit, block) = exclusive sum of the
 //      totals of the smaller digits + the scanned hist entry; stable
-//      ranking, reorder by digit in LDS, then a write
-//      in LDS order: consecutive lanes store consecutive addresses of one
-//      digit's run (coalesced), instead of 64 scattered 4-byte stores.
+//      ranking, reorder by digit in LDS, then a write in LDS order:
+//      consecutive lanes store consecutive addresses of one digit's run
+//      (coalesced), instead of 64 scattered 4-byte stores.
 // Each workgroup owns SORT_ITEMS consecutive pairs; wave w owns the w-th
 // quarter and walks it in 64-item rounds, so the rank of an item among equal
 // digits follows input order (stability).
