@@ -184,7 +184,7 @@ void launch_bin_sort(const BinArgs& a, const BinWs& w, hipStream_t st) {
   const int start = (passes & 1) ? 0 : 1;
   k_dup<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), w.cnt, m,
                                  a.n_max, a.tiles_x, tiles, a.n_entries, K[start], Vv[start]);
-  const int ecur = radix_sort_pairs(K, Vv, start, a.n_entries, passes * 8, w.temp, st);
+  const int ecur = radix_sort_pairs(K, Vv, start, a.n_entries, bits, w.temp, st);
   // 4. per-tile ranges
   k_zero_words<<<nblk(nranges), 256, 0, st>>>(a.ranges, nranges);
   if (a.n_entries > 0)

@@ -35,9 +35,10 @@ void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* 
 // ---- sort.hip
 constexpr int SORT_ITEMS = 4096;   // items per workgroup and pass
 size_t radix_temp_elems(int64_t n);
-// Stable LSD radix sort of (key, value) pairs by key bits [0, bits), 8 bits
-// per pass, ping-ponging between (k[0], v[0]) and (k[1], v[1]); the input is
-// in slot `start`; returns the slot that holds the result.
+// Stable LSD radix sort of (key, value) pairs by key bits [0, bits) (the
+// other bits must be zero), ceil(bits / 8) passes sharing the bits evenly,
+// ping-ponging between (k[0], v[0]) and (k[1], v[1]); the input is in slot
+// `start`; returns the slot that holds the result.
 int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
                      uint32_t* temp, hipStream_t s);
 

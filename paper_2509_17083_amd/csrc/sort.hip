@@ -1,5 +1,6 @@
-// Stable LSD radix sort of (uint32 key, uint32 value) pairs, 8-bit digits,
-// reduce-then-scan per pass (no inter-workgroup waiting), three launches:
+// Stable LSD radix sort of (uint32 key, uint32 value) pairs, digits of at
+// most 8 bits, reduce-then-scan per pass (no inter-workgroup waiting), three
+// launches per pass:
 //   1. per-workgroup digit histogram -> hist[digit * nblocks + block]
 //   2. one workgroup per digit: exclusive scan of the digit's row of hist
 //      over the workgroups, in place, and the row's total -> tot[digit]
@@ -23,7 +24,7 @@ constexpr int ROUNDS = SORT_ITEMS / NT;       // 16 rounds of 64 per wave
 constexpr int RADIX = 256;
 
 __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
-                                                   int shift, uint32_t* __restrict__ hist,
+                                                   int shift, uint32_t mask, uint32_t* __restrict__ hist,
                                                    int nblocks) {
   __shared__ uint32_t h[RADIX];
   h[threadIdx.x] = 0;
@@ -33,7 +34,7 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ 
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
     const int64_t i = base + (int64_t)r * NT + threadIdx.x;
-    d[r] = i < n ? (keys[i] >> shift) & 0xFFu : RADIX;
+    d[r] = i < n ? (keys[i] >> shift) & mask : RADIX;
   }
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r)
@@ -75,7 +76,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout,
                                                       uint32_t* __restrict__ vout, int64_t n,
-                                                      int shift, const uint32_t* __restrict__ hist,
+                                                      int shift, uint32_t mask,
+                                                      const uint32_t* __restrict__ hist,
                                                       const uint32_t* __restrict__ dtot, int nblocks) {
   static_assert(NT == RADIX, "one thread per digit");
   __shared__ uint32_t cnt[NW][RADIX];
@@ -97,7 +99,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     uint32_t k = ok ? kin[i] : 0u;
     key[r] = k;
     val[r] = ok ? vin[i] : 0u;
-    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t d = (k >> shift) & mask;
     // lanes holding the same digit (out-of-range lanes form their own group)
     uint64_t m = __ballot(ok);
     if (!ok) m = ~m;
@@ -132,7 +134,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
   for (int r = 0; r < ROUNDS; ++r) {
     const int64_t i = chunk + (int64_t)r * WAVE + lane;
     if (i < n) {
-      const uint32_t d = (key[r] >> shift) & 0xFFu;
+      const uint32_t d = (key[r] >> shift) & mask;
       const uint32_t lp = lstart[d] + cnt[w][d] + rank[r];
       sk[lp] = key[r];
       sv[lp] = val[r];
@@ -143,7 +145,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
   const int m = (int)min((int64_t)SORT_ITEMS, n - base);
   for (int t = threadIdx.x; t < m; t += NT) {
     const uint32_t k = sk[t];
-    const uint32_t d = (k >> shift) & 0xFFu;
+    const uint32_t d = (k >> shift) & mask;
     const uint32_t pos = gbase[d] + ((uint32_t)t - lstart[d]);
     kout[pos] = k;
     vout[pos] = sv[t];
@@ -162,14 +164,20 @@ int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int b
   if (n <= 1 || bits <= 0) return start;
   if (bits > 32) bits = 32;
   const int nb = (int)((n + SORT_ITEMS - 1) / SORT_ITEMS);
+  // as few passes as 8-bit digits need, the bits shared out evenly: fewer
+  // distinct digits per pass give longer runs per digit in each workgroup's
+  // output, so its stores fill whole lines
   const int passes = (bits + 7) / 8;
   uint32_t* hist = temp;
   uint32_t* tot = temp + (size_t)nb * RADIX;   // [RADIX] digit totals of the pass
-  int cur = start;
+  int cur = start, shift = 0;
   for (int p = 0; p < passes; ++p) {
-    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, 8 * p, hist, nb);
+    const int w = bits / passes + (p < bits % passes ? 1 : 0);
+    const uint32_t mask = (1u << w) - 1u;
+    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, shift, mask, hist, nb);
     k_radix_offsets<<<RADIX, NT, 0, st>>>(hist, tot, nb);
-    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, 8 * p, hist, tot, nb);
+    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, mask, hist, tot, nb);
+    shift += w;
     cur ^= 1;
   }
   return cur;
