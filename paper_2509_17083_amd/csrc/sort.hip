@@ -2,7 +2,8 @@
 // most 8 bits, reduce-then-scan per pass (no inter-workgroup waiting), three
 // launches per pass:
 //   1. per-workgroup digit histogram -> hist[digit * nblocks + block]
-//   2. one workgroup per digit: exclusive scan of the digit's row of hist
+//      (rows of the digits the pass uses: 2^width of them)
+//   2. one workgroup per used digit: exclusive scan of the digit's row of hist
 //      over the workgroups, in place, and the row's total -> tot[digit]
 //   3. per workgroup: global base of (digit, block) = exclusive sum of the
 //      totals of the smaller digits + the scanned hist entry; stable
@@ -40,7 +41,7 @@ __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ 
   for (int r = 0; r < ROUNDS; ++r)
     if (d[r] < RADIX) atomicAdd(&h[d[r]], 1u);
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x <= mask) hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
 // Workgroup d: hist[d * nblocks + b] <- number of keys with digit d in the
@@ -127,7 +128,9 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     }
     uint32_t all;
     lstart[d] = block_excl_scan<NT>(tot, scan_sh, &all);
-    gbase[d] = block_excl_scan<NT>(dtot[d], scan_sh, &all) + hist[(int64_t)d * nblocks + blockIdx.x];
+    const bool used = (uint32_t)d <= mask;   // rows of digits the pass cannot produce are not written
+    gbase[d] = block_excl_scan<NT>(used ? dtot[d] : 0u, scan_sh, &all) +
+               (used ? hist[(int64_t)d * nblocks + blockIdx.x] : 0u);
   }
   __syncthreads();
 #pragma unroll
@@ -175,7 +178,7 @@ int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int b
     const int w = bits / passes + (p < bits % passes ? 1 : 0);
     const uint32_t mask = (1u << w) - 1u;
     k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, shift, mask, hist, nb);
-    k_radix_offsets<<<RADIX, NT, 0, st>>>(hist, tot, nb);
+    k_radix_offsets<<<mask + 1, NT, 0, st>>>(hist, tot, nb);
     k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, mask, hist, tot, nb);
     shift += w;
     cur ^= 1;
