@@ -18,6 +18,7 @@ struct BinWs {
   uint32_t* dk[2];
   uint32_t* dv[2];
   uint32_t* cnt;
+  int4* srect;          // tile rectangles in depth order
   uint32_t* ek[2];
   uint32_t* ev;
   uint32_t* temp;

@@ -31,19 +31,19 @@ __global__ __launch_bounds__(256) void k_depth_keys(const float* __restrict__ de
   val[i] = (uint32_t)i;
 }
 
-// number of tile entries of the splat at each depth-sorted position
+// number of tile entries of the splat at each depth-sorted position, and its
+// rectangle stored in depth order (one random gather here; the entry
+// expansion then reads the rectangles in order)
 __global__ __launch_bounds__(256) void k_tile_counts(const uint32_t* __restrict__ skey,
                                                      const uint32_t* __restrict__ sval,
                                                      const int4* __restrict__ rect, int64_t m,
-                                                     uint32_t* __restrict__ cnt) {
+                                                     uint32_t* __restrict__ cnt, int4* __restrict__ srect) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= m) return;
-  uint32_t c = 0;
-  if (skey[i] != 0xFFFFFFFFu) {
-    const int4 r = rect[sval[i]];
-    c = (uint32_t)((r.z - r.x) * (r.w - r.y));
-  }
-  cnt[i] = c;
+  int4 r = make_int4(0, 0, 0, 0);
+  if (skey[i] != 0xFFFFFFFFu) r = rect[sval[i]];
+  cnt[i] = (uint32_t)((r.z - r.x) * (r.w - r.y));
+  srect[i] = r;
 }
 
 // write the entries of each splat in depth order: key = view*tiles + tile.
@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void k_tile_counts(const uint32_t* __restrict_
 // stores, large splats spread over all lanes).
 __global__ __launch_bounds__(256) void k_dup(const uint32_t* __restrict__ skey,
                                              const uint32_t* __restrict__ sval,
-                                             const int4* __restrict__ rect,
+                                             const int4* __restrict__ srect,
                                              const uint32_t* __restrict__ off, int64_t m, int n_max,
                                              int tiles_x, int tiles, int64_t capacity,
                                              uint32_t* __restrict__ ekey, uint32_t* __restrict__ eval) {
@@ -67,7 +67,7 @@ __global__ __launch_bounds__(256) void k_dup(const uint32_t* __restrict__ skey,
   if (i0 >= m) return;                            // whole wave idle (uniform)
   const bool ok = i < m && skey[i] != 0xFFFFFFFFu;
   const uint32_t id = ok ? sval[i] : 0u;
-  const int4 r = ok ? rect[id] : make_int4(0, 0, 0, 0);
+  const int4 r = ok ? srect[i] : make_int4(0, 0, 0, 0);
   const uint32_t cnt = ok ? (uint32_t)((r.z - r.x) * (r.w - r.y)) : 0u;
   const uint32_t first = off[i0];
   const uint32_t rel = i < m ? off[i] - first : 0u;
@@ -147,6 +147,7 @@ BinWs carve_bin_ws(void* ws, int V, int n_max, int64_t capacity, int tiles_total
   w.dv[0] = c.take<uint32_t>(m);
   w.dv[1] = c.take<uint32_t>(m);
   w.cnt = c.take<uint32_t>(m);
+  w.srect = c.take<int4>(m);
   w.ek[0] = c.take<uint32_t>(capacity > 0 ? capacity : 1);
   w.ek[1] = c.take<uint32_t>(capacity > 0 ? capacity : 1);
   w.ev = c.take<uint32_t>(capacity > 0 ? capacity : 1);
@@ -174,7 +175,8 @@ void launch_bin_sort(const BinArgs& a, const BinWs& w, hipStream_t st) {
   uint32_t* dv[2] = {w.dv[0], w.dv[1]};
   const int dcur = radix_sort_pairs(dk, dv, 0, m, 32, w.temp, st);
   // 2. entry offsets in depth order
-  k_tile_counts<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), m, w.cnt);
+  k_tile_counts<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), m, w.cnt,
+                                         w.srect);
   scan_exclusive_u32(w.cnt, w.cnt, m, w.temp, nullptr, st);
   // 3. entries, then a stable sort by (view, tile)
   const int bits = key_bits_for((int64_t)a.V * tiles);
@@ -182,7 +184,7 @@ void launch_bin_sort(const BinArgs& a, const BinWs& w, hipStream_t st) {
   uint32_t* K[2] = {w.ek[0], a.keys ? a.keys : w.ek[1]};
   uint32_t* Vv[2] = {w.ev, a.vals};
   const int start = (passes & 1) ? 0 : 1;
-  k_dup<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], reinterpret_cast<const int4*>(a.rect), w.cnt, m,
+  k_dup<<<nblk(m), 256, 0, st>>>(dk[dcur], dv[dcur], w.srect, w.cnt, m,
                                  a.n_max, a.tiles_x, tiles, a.n_entries, K[start], Vv[start]);
   const int ecur = radix_sort_pairs(K, Vv, start, a.n_entries, bits, w.temp, st);
   // 4. per-tile ranges
