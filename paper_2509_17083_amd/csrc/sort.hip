@@ -10,7 +10,7 @@
 //      ranking, reorder by digit in LDS, then a write in LDS order:
 //      consecutive lanes store consecutive addresses of one digit's run
 //      (coalesced), instead of 64 scattered 4-byte stores.
-// Each workgroup owns SORT_ITEMS consecutive pairs; wave w owns the w-th
+// Each workgroup owns ITEMS consecutive pairs; wave w owns the w-th
 // quarter and walks it in 64-item rounds, so the rank of an item among equal
 // digits follows input order (stability).
 #include "block.h"
@@ -21,16 +21,17 @@ namespace hyrf {
 namespace {
 constexpr int NT = 256;
 constexpr int NW = NT / WAVE;                 // 4 waves
-constexpr int ROUNDS = SORT_ITEMS / NT;       // 16 rounds of 64 per wave
 constexpr int RADIX = 256;
 
+template <int ITEMS>
 __global__ __launch_bounds__(NT) void k_radix_hist(const uint32_t* __restrict__ keys, int64_t n,
                                                    int shift, uint32_t mask, uint32_t* __restrict__ hist,
                                                    int nblocks) {
+  constexpr int ROUNDS = ITEMS / NT;
   __shared__ uint32_t h[RADIX];
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
+  const int64_t base = (int64_t)blockIdx.x * ITEMS;
   uint32_t d[ROUNDS];   // all loads in flight before the first LDS update
 #pragma unroll
   for (int r = 0; r < ROUNDS; ++r) {
@@ -73,6 +74,7 @@ __global__ __launch_bounds__(NT) void k_radix_offsets(uint32_t* __restrict__ his
   if (threadIdx.x == 0) tot[d] = carry;
 }
 
+template <int ITEMS>
 __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict__ kin,
                                                       const uint32_t* __restrict__ vin,
                                                       uint32_t* __restrict__ kout,
@@ -81,8 +83,10 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
                                                       const uint32_t* __restrict__ hist,
                                                       const uint32_t* __restrict__ dtot, int nblocks) {
   static_assert(NT == RADIX, "one thread per digit");
+  static_assert(ITEMS % NT == 0, "whole rounds of 64 per wave");
+  constexpr int ROUNDS = ITEMS / NT;
   __shared__ uint32_t cnt[NW][RADIX];
-  __shared__ uint32_t sk[SORT_ITEMS], sv[SORT_ITEMS];   // the workgroup's pairs, ordered by digit
+  __shared__ uint32_t sk[ITEMS], sv[ITEMS];   // the workgroup's pairs, ordered by digit
   __shared__ uint32_t lstart[RADIX], gbase[RADIX];
   __shared__ uint32_t scan_sh[NW + 1];
   const int lane = lane_id();
@@ -90,7 +94,7 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
   for (int k = threadIdx.x; k < NW * RADIX; k += NT) (&cnt[0][0])[k] = 0;
   __syncthreads();
 
-  const int64_t chunk = (int64_t)blockIdx.x * SORT_ITEMS + (int64_t)w * (ROUNDS * WAVE);
+  const int64_t chunk = (int64_t)blockIdx.x * ITEMS + (int64_t)w * (ROUNDS * WAVE);
   const uint64_t lt = (1ull << lane) - 1ull;
   uint32_t key[ROUNDS], val[ROUNDS], rank[ROUNDS];
 #pragma unroll
@@ -144,8 +148,8 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
     }
   }
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * SORT_ITEMS;
-  const int m = (int)min((int64_t)SORT_ITEMS, n - base);
+  const int64_t base = (int64_t)blockIdx.x * ITEMS;
+  const int m = (int)min((int64_t)ITEMS, n - base);
   for (int t = threadIdx.x; t < m; t += NT) {
     const uint32_t k = sk[t];
     const uint32_t d = (k >> shift) & mask;
@@ -156,17 +160,26 @@ __global__ __launch_bounds__(NT) void k_radix_scatter(const uint32_t* __restrict
 }
 }  // namespace
 
+// Sorts of up to SORT_SMALL_N pairs give each workgroup SORT_ITEMS_SMALL of
+// them, so that they still spread over every CU; larger ones SORT_ITEMS.
+constexpr int SORT_ITEMS_SMALL = 1024;
+constexpr int64_t SORT_SMALL_N = (int64_t)1 << 21;
+
+static int64_t sort_blocks(int64_t n, int items) { return (n + items - 1) / items; }
+
 size_t radix_temp_elems(int64_t n) {
-  int64_t nb = (n + SORT_ITEMS - 1) / SORT_ITEMS;
+  // enough for any sort of at most n pairs, in either workgroup size
+  int64_t nb = sort_blocks(n, SORT_ITEMS);
+  const int64_t nb_small = sort_blocks(n < SORT_SMALL_N ? n : SORT_SMALL_N, SORT_ITEMS_SMALL);
+  if (nb_small > nb) nb = nb_small;
   if (nb < 1) nb = 1;
   return (size_t)nb * RADIX + RADIX;
 }
 
-int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
-                     uint32_t* temp, hipStream_t st) {
-  if (n <= 1 || bits <= 0) return start;
-  if (bits > 32) bits = 32;
-  const int nb = (int)((n + SORT_ITEMS - 1) / SORT_ITEMS);
+template <int ITEMS>
+static int radix_passes(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits, uint32_t* temp,
+                        hipStream_t st) {
+  const int nb = (int)sort_blocks(n, ITEMS);
   // as few passes as 8-bit digits need, the bits shared out evenly: fewer
   // distinct digits per pass give longer runs per digit in each workgroup's
   // output, so its stores fill whole lines
@@ -177,13 +190,22 @@ int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int b
   for (int p = 0; p < passes; ++p) {
     const int w = bits / passes + (p < bits % passes ? 1 : 0);
     const uint32_t mask = (1u << w) - 1u;
-    k_radix_hist<<<nb, NT, 0, st>>>(k[cur], n, shift, mask, hist, nb);
+    k_radix_hist<ITEMS><<<nb, NT, 0, st>>>(k[cur], n, shift, mask, hist, nb);
     k_radix_offsets<<<mask + 1, NT, 0, st>>>(hist, tot, nb);
-    k_radix_scatter<<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, mask, hist, tot, nb);
+    k_radix_scatter<ITEMS><<<nb, NT, 0, st>>>(k[cur], v[cur], k[cur ^ 1], v[cur ^ 1], n, shift, mask, hist,
+                                              tot, nb);
     shift += w;
     cur ^= 1;
   }
   return cur;
+}
+
+int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int bits,
+                     uint32_t* temp, hipStream_t st) {
+  if (n <= 1 || bits <= 0) return start;
+  if (bits > 32) bits = 32;
+  if (n <= SORT_SMALL_N) return radix_passes<SORT_ITEMS_SMALL>(k, v, start, n, bits, temp, st);
+  return radix_passes<SORT_ITEMS>(k, v, start, n, bits, temp, st);
 }
 
 }  // namespace hyrf
