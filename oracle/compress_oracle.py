@@ -6,7 +6,7 @@ TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's
 CPU-baseline leg call this module; the product path never imports it, and
 this module imports nothing from the product.
 
-Readings of what the paper leaves open (each also listed in the design doc):
+Readings of what the paper leaves open:
   * min and max are taken per level of each table, over both features of
     every entry; the 256 codes span [min, max] evenly:
     step = (max - min) / 255, code = round((x - min) / step), decoded value

@@ -18,7 +18,7 @@ paper's order:
   Eq. 12, L1 term).  Gradients are the exact derivative of this forward,
   taken by torch autograd in float64 (predicates and floors held fixed).
 
-Readings of passages the paper leaves open (each also listed in the design doc):
+Readings of passages the paper leaves open:
   * contraction maps onto (0,1) with x = 0.25*m + 0.5 (the printed "+1"
     contradicts the stated (0,1) range);
   * the scene box normalisation is p' = (p - centre) * inv_half_extent;

@@ -16,7 +16,7 @@ periodically reset and low-opacity Gaussians pruned (Sec. 3.1, Sec. 3.4):
 Adam (Kingma & Ba 2015, Algorithm 1), the 3DGS densification statistics and
 decisions, the opacity reset.
 
-Readings of what the paper leaves open (each also listed in the design doc):
+Readings of what the paper leaves open:
   * the SSIM term of Eq. 12 is the structural dissimilarity 1 - SSIM (a loss
     that is minimised), with the 3DGS settings: lambda = 0.2; an 11 x 11
     Gaussian window of standard deviation 1.5; stabilisers C1 = (0.01 L)^2,
