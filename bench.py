@@ -325,13 +325,19 @@ def main():
     # Roofline of the dominant kernel of the train step: the background
     # points' adjoint (k_field_bwd in ray mode: colour decoder on MFMA, then
     # the radiance-table scatter; alone in backward stage 4 of the serial
-    # run).  Algorithmic bytes per background pixel: the saved features read
-    # (2L floats), T_final and dL/dC read (4 floats), and for each of L
-    # levels x 8 corners one read-modify-write of the 2-float table row (16 B).
+    # run).  Algorithmic bytes per background pixel: the scatter payload of
+    # the radiance-table gradient, L levels x 8 corners x 2 features x 4 B
+    # (1 KB at L = 16).  Beside it: the same kernel against the MFMA peak
+    # (adjoint of the colour decoder = 2x its forward FLOPs per pixel) and
+    # against the measured atomic-request rate, which is what binds it.
     n_bg = V * H * W
-    per_px = 2 * cfg.levels * 4 + 4 * 4 + cfg.levels * 8 * 16
+    per_px = cfg.levels * 8 * 2 * 4
+    per_px_rmw = 2 * cfg.levels * 4 + 4 * 4 + cfg.levels * 8 * 16
+    col_fwd_flop = 2.0 * (cfg.hidden * (2 * cfg.levels + 24) + (cfg.n_hidden - 1) * cfg.hidden * cfg.hidden
+                          + 3 * cfg.hidden)
     bg_ms = st_serial["bwd_bg"]
     ach = n_bg * per_px / (bg_ms * 1e-3) / 1e9
+    mfma_tf = 2.0 * col_fwd_flop * n_bg / (bg_ms * 1e-3) / 1e12
     # the scatter's real bound: float atomics.  Reference rate: torch's
     # index_add_ of 64M values at random indices of a 256 MB buffer (one
     # float atomic per value); the kernel issues L x 8 corners x 2 features
@@ -356,7 +362,7 @@ def main():
     # summary) against that measured rate: the scatter's own roofline
     req = measured_traffic("k_field_bwd_bg", "l2_atomic_requests")
     if req:
-        atomics.update({"l2_atomic_requests_per_launch": req,
+        atomics.update({"l2_atomic_requests_per_launch": req, "requests_per_pixel": round(req / n_bg, 2),
                         "requests_per_s": round(req / (bg_ms * 1e-3) / 1e9, 1),
                         "frac_of_measured_atomic_rate": round(req / (bg_ms * 1e-3) / atomic_rate, 3)})
     roof = {"kernel": "k_field_bwd (background points)", "bound": "hbm", "achieved": round(ach, 1),
@@ -364,6 +370,9 @@ def main():
             "traffic": measured_traffic("k_field_bwd_bg"),
             "algorithmic_bytes": n_bg * per_px,
             "bytes_per_pixel": per_px, "pixels": n_bg, "kernel_ms": round(bg_ms, 4),
+            "bytes_per_pixel_read_modify_write": per_px_rmw,
+            "mfma": {"flop_per_pixel": 2.0 * col_fwd_flop, "achieved_TFLOPs": round(mfma_tf, 2),
+                     "peak_TFLOPs": MFMA_F32_PEAK, "frac": round(mfma_tf / MFMA_F32_PEAK, 4)},
             "share_of_step": round(bg_ms / ms_train, 3), "atomics": atomics}
     # the dominant forward kernel: the field query (gather-bound); bytes per
     # surviving Gaussian = 2 fields x L levels x 8 corners x 2 features x 4 B

@@ -274,35 +274,70 @@ def splat_extent(cov2d: torch.Tensor, opacity: torch.Tensor):
 
 
 # ---------------------------------------------------------------- compositing
-def _pairs_for_pixels(px, py, u, v, rx, ry):
-    """All (pixel, splat) pairs whose conservative box holds the pixel centre.
-    Pixels are grouped by 16x16 block; a block's candidates are the splats
-    whose box meets the block, then every pixel of the block is tested."""
+def _pairs_for_pixels(px, py, u, v, rx, ry, chunk=1 << 22):
+    """All (pixel, splat) pairs whose conservative box holds the pixel centre:
+    |px + .5 - u| <= rx and |py + .5 - v| <= ry.  No tiling: candidates come
+    either from each splat's own box, enumerated pixel by pixel over the
+    rectangle spanned by the requested pixels, or (when fewer) from every
+    (pixel, splat) combination; the predicate above then decides."""
+    P, N = px.numel(), u.numel()
+    empty = (torch.zeros(0, dtype=torch.int64), torch.zeros(0, dtype=torch.int64))
+    if P == 0 or N == 0:
+        return empty
+    cxp = px.to(F64) + 0.5
+    cyp = py.to(F64) + 0.5
+
+    def exact(pi, si):
+        m = (torch.abs(cxp[pi] - u[si]) <= rx[si]) & (torch.abs(cyp[pi] - v[si]) <= ry[si])
+        return pi[m], si[m]
+
+    xmin, xmax = int(px.min()), int(px.max())
+    ymin, ymax = int(py.min()), int(py.max())
+    # each splat's box in pixel indices, widened by one pixel against rounding
+    # (the exact predicate decides), clipped to the requested rectangle
+    x0 = torch.clamp(torch.floor(u - rx - 0.5) - 1, min=xmin)
+    x1 = torch.clamp(torch.ceil(u + rx - 0.5) + 1, max=xmax)
+    y0 = torch.clamp(torch.floor(v - ry - 0.5) - 1, min=ymin)
+    y1 = torch.clamp(torch.ceil(v + ry - 0.5) + 1, max=ymax)
+    nx = torch.clamp(x1 - x0 + 1, min=0).to(torch.int64)
+    ny = torch.clamp(y1 - y0 + 1, min=0).to(torch.int64)
+    nx = torch.where(rx >= 0, nx, torch.zeros_like(nx))
+    area = nx * ny
     pi_list, si_list = [], []
-    bx = torch.div(px, 16, rounding_mode="floor")
-    by = torch.div(py, 16, rounding_mode="floor")
-    bid = by * (int(bx.max().item()) + 2 if px.numel() else 1) + bx
-    order = torch.argsort(bid, stable=True)
-    ub, counts = torch.unique_consecutive(bid[order], return_counts=True)
-    starts = torch.cumsum(counts, 0) - counts
-    for k in range(ub.numel()):
-        sel = order[starts[k]:starts[k] + counts[k]]
-        x0 = float(px[sel].min()) + 0.5
-        x1 = float(px[sel].max()) + 0.5
-        y0 = float(py[sel].min()) + 0.5
-        y1 = float(py[sel].max()) + 0.5
-        cand = torch.nonzero((u + rx >= x0) & (u - rx <= x1) & (v + ry >= y0) & (v - ry <= y1),
-                             as_tuple=True)[0]
-        if cand.numel() == 0:
-            continue
-        cx = px[sel, None].to(F64) + 0.5
-        cy = py[sel, None].to(F64) + 0.5
-        m = (torch.abs(cx - u[None, cand]) <= rx[None, cand]) & (torch.abs(cy - v[None, cand]) <= ry[None, cand])
-        a, b = torch.nonzero(m, as_tuple=True)
-        pi_list.append(sel[a])
-        si_list.append(cand[b])
+    unique = torch.unique((py - ymin) * (xmax - xmin + 1) + (px - xmin)).numel() == P
+    if unique and int(area.sum()) <= P * N:
+        Wb = xmax - xmin + 1
+        lut = torch.full(((ymax - ymin + 1) * Wb,), -1, dtype=torch.int64)
+        lut[(py - ymin) * Wb + (px - xmin)] = torch.arange(P)
+        csum = torch.cumsum(area, 0)
+        s0 = 0
+        while s0 < N:
+            base = int(csum[s0 - 1]) if s0 else 0
+            s1 = int(torch.searchsorted(csum, torch.tensor(base + chunk, dtype=csum.dtype), right=True))
+            s1 = max(s1, s0 + 1)
+            sel = torch.arange(s0, min(s1, N))
+            cnt = area[sel]
+            si = torch.repeat_interleave(sel, cnt)
+            k = torch.arange(si.numel()) - torch.repeat_interleave(torch.cumsum(cnt, 0) - cnt, cnt)
+            xx = x0[si].to(torch.int64) + k % nx[si]
+            yy = y0[si].to(torch.int64) + torch.div(k, nx[si], rounding_mode="floor")
+            pi = lut[(yy - ymin) * Wb + (xx - xmin)]
+            keep = pi >= 0
+            a, b = exact(pi[keep], si[keep])
+            pi_list.append(a)
+            si_list.append(b)
+            s0 = min(s1, N)
+    else:
+        step = max(1, chunk // N)
+        for p0 in range(0, P, step):
+            pp = torch.arange(p0, min(P, p0 + step))
+            pi = pp.repeat_interleave(N)
+            si = torch.arange(N).repeat(pp.numel())
+            a, b = exact(pi, si)
+            pi_list.append(a)
+            si_list.append(b)
     if not pi_list:
-        return torch.zeros(0, dtype=torch.int64), torch.zeros(0, dtype=torch.int64)
+        return empty
     return torch.cat(pi_list), torch.cat(si_list)
 
 
@@ -490,10 +525,100 @@ def render_view(params: Params, fields: Fields, cam, mode: int = TRAIN,
     if bool(need.any()):
         cs = background_colour(px[need], py[need], cam, fields)
         out = out.index_put((torch.nonzero(need, as_tuple=True)[0],), C_fg[need] + T_final[need, None] * cs)
-    result = dict(rgb=out, rgb_fg=C_fg, T=T_final, vis_idx=idx, query=q, proj=pr, depth_key=dk, px=px, py=py)
+    result = dict(rgb=out, rgb_fg=C_fg, T=T_final, vis_idx=idx, query=q, proj=pr, depth_key=dk, px=px, py=py,
+                  rank=rank, rx=rx, ry=ry, mode=mode, cam=cam, fields=fields, bg_added=need)
     if return_stats:
         result["stats"] = res[2]
     return result
+
+
+# ---------------------------------------------------------------- decision variants
+def blend_pixel(alpha, power, rgb, flip_alpha: int = -1, flip_stop: int = -1):
+    """Front-to-back blending of one pixel (Sec. 3.1 Eq. 1 with the 3DGS
+    rules) over its depth-ordered pairs, in plain Python, with at most one
+    decision negated: the contribution test of pair `flip_alpha`
+    (alpha >= 1/255 and power <= 0) or the early-stop test at pair
+    `flip_stop` (stop before T (1 - alpha) < 1e-4).  alpha: the clamped
+    min(0.99, o e^power) per pair.  Returns (C_fg[3], T_final)."""
+    T = 1.0
+    C = [0.0, 0.0, 0.0]
+    for j, (a, pw, c) in enumerate(zip(alpha, power, rgb)):
+        take = (a >= ALPHA_MIN) and (pw <= 0.0)
+        if j == flip_alpha:
+            take = not take
+        if not take:
+            continue
+        tT = T * (1.0 - a)
+        stop = tT < T_EPS
+        if j == flip_stop:
+            stop = not stop
+        if stop:
+            break
+        for ch in range(3):
+            C[ch] += c[ch] * a * T
+        T = tT
+    return C, T
+
+
+def decision_variants(r, ks, delta_alpha: float, delta_T: float):
+    """For pixels `ks` (indices into r['px']) of a render_view result r: the
+    oracle's colour, and the colour the same pixel takes when ONE of its
+    threshold decisions that lies within a relative distance delta of its
+    threshold is taken the other way -- a pair's alpha >= 1/255 test
+    (|255 alpha - 1| < delta_alpha), an early-stop test
+    (|T (1 - alpha) / 1e-4 - 1| < delta_T) or, in render mode, the background
+    test T_final > tau_T (|T_final / tau_T - 1| < delta_T).  Colours include
+    the background term of Sec. 3.3 Eq. 10.  Returns, per pixel, a list of
+    (kind, pair, distance, rgb[3]) with kind 'base', 'alpha', 'stop' or 'tau'
+    and distance the decision's relative distance from its threshold."""
+    ks = torch.as_tensor(ks, dtype=torch.int64)
+    if ks.numel() == 0:
+        return []
+    q, pr, cam, fields = r["query"], r["proj"], r["cam"], r["fields"]
+    with torch.no_grad():
+        px, py = r["px"][ks], r["py"][ks]
+        u, v, conic = pr["u"].detach(), pr["v"].detach(), pr["conic"].detach()
+        opac, rgb = q["opacity"].detach(), q["rgb"].detach()
+        pi, si = _pairs_for_pixels(px, py, u, v, r["rx"].detach(), r["ry"].detach())
+        cs = background_colour(px, py, cam, fields)
+    out = []
+    for m in range(ks.numel()):
+        s = si[pi == m]
+        s = s[torch.argsort(r["rank"][s])]
+        dx = u[s] - (float(px[m]) + 0.5)
+        dy = v[s] - (float(py[m]) + 0.5)
+        power = -0.5 * (conic[s, 0] * dx * dx + conic[s, 2] * dy * dy) - conic[s, 1] * dx * dy
+        alpha = torch.clamp(opac[s] * torch.exp(power), max=ALPHA_MAX)
+        al, pw, cl = alpha.tolist(), power.tolist(), rgb[s].tolist()
+        c_s = cs[m].tolist()
+
+        def full(C, T, tau_flip=False):
+            bg = True if r["mode"] == TRAIN else (T > fields.tau_T)
+            if tau_flip:
+                bg = not bg
+            return [C[ch] + (T * c_s[ch] if bg else 0.0) for ch in range(3)]
+        C0, T0 = blend_pixel(al, pw, cl)
+        var = [("base", -1, 0.0, full(C0, T0))]
+        T = 1.0
+        for j in range(len(al)):
+            take = al[j] >= ALPHA_MIN and pw[j] <= 0.0
+            da = abs(255.0 * al[j] - 1.0)
+            if da < delta_alpha:
+                var.append(("alpha", j, da, full(*blend_pixel(al, pw, cl, flip_alpha=j))))
+            if not take:
+                continue
+            tT = T * (1.0 - al[j])
+            dt = abs(tT / T_EPS - 1.0)
+            if dt < delta_T:
+                var.append(("stop", j, dt, full(*blend_pixel(al, pw, cl, flip_stop=j))))
+            if tT < T_EPS:
+                break
+            T = tT
+        dtau = abs(T0 / fields.tau_T - 1.0)
+        if r["mode"] == RENDER and dtau < delta_T:
+            var.append(("tau", -1, dtau, full(C0, T0, tau_flip=True)))
+        out.append(var)
+    return out
 
 
 def render_image(params, fields, cam, mode=TRAIN, return_stats=False):

@@ -135,8 +135,7 @@ def test_fp32_and_variant_on_the_1080p_crop():
         res[name] = dict(img=img, psnr_vs_fp64=psnr(img, ref_img), psnr_target=psnr(img, tgt), grad_rel=errs)
         print(name, "PSNR vs FP64 %.2f dB" % res[name]["psnr_vs_fp64"], "gradient rel. L2",
               {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    c = compare_image(res["fp32"]["img"], {"rgb": r["rgb"].detach(), "T": r["T"].detach(), "stats": r["stats"]},
-                      O.TRAIN, H, W)
+    c = compare_image(res["fp32"]["img"], r, O.TRAIN, H, W)
     assert c["ok"], c
     assert all(e < 1e-3 for e in res["fp32"]["grad_rel"].values()), res["fp32"]["grad_rel"]
     d = res["f16+bf16"]["psnr_target"] - res["fp32"]["psnr_target"]

@@ -467,3 +467,187 @@ def test_oracle_gradient_matches_central_differences():
             assert abs(fd - float(gflat[j])) <= 1e-5 * max(1.0, abs(fd)), (leaf.shape, j, fd, float(gflat[j]))
             checked += 1
     assert checked >= 30
+
+
+# ------------------------------------------------------------ rotation / camera centre
+def _rodrigues(axis, theta):
+    """Rotation by theta about the unit axis: I cos t + sin t [n]x + (1 - cos t) n n^T."""
+    n = np.asarray(axis, np.float64)
+    n = n / np.linalg.norm(n)
+    K = np.array([[0.0, -n[2], n[1]], [n[2], 0.0, -n[0]], [-n[1], n[0], 0.0]])
+    return np.eye(3) * math.cos(theta) + math.sin(theta) * K + (1 - math.cos(theta)) * np.outer(n, n)
+
+
+def test_quat_to_rot_closed_forms():
+    # q = (w, x, y, z) = (cos t/2, sin t/2 n): rotation by t about n, applied to column vectors
+    th = 0.7
+    Rz = O.quat_to_rot(torch.tensor([[math.cos(th / 2), 0.0, 0.0, math.sin(th / 2)]], dtype=F64))[0]
+    assert torch.allclose(Rz @ torch.tensor([1.0, 0, 0], dtype=F64),
+                          torch.tensor([math.cos(th), math.sin(th), 0.0], dtype=F64), atol=1e-15)
+    assert torch.allclose(Rz @ torch.tensor([0, 1.0, 0], dtype=F64),
+                          torch.tensor([-math.sin(th), math.cos(th), 0.0], dtype=F64), atol=1e-15)
+    Rx = O.quat_to_rot(torch.tensor([[math.cos(th / 2), math.sin(th / 2), 0.0, 0.0]], dtype=F64))[0]
+    assert torch.allclose(Rx @ torch.tensor([0, 1.0, 0], dtype=F64),
+                          torch.tensor([0.0, math.cos(th), math.sin(th)], dtype=F64), atol=1e-15)
+    Ry = O.quat_to_rot(torch.tensor([[math.cos(th / 2), 0.0, math.sin(th / 2), 0.0]], dtype=F64))[0]
+    assert torch.allclose(Ry @ torch.tensor([0, 0, 1.0], dtype=F64),
+                          torch.tensor([math.sin(th), 0.0, math.cos(th)], dtype=F64), atol=1e-15)
+    # half turn about x
+    assert torch.allclose(O.quat_to_rot(torch.tensor([[0.0, 1.0, 0.0, 0.0]], dtype=F64))[0],
+                          torch.diag(torch.tensor([1.0, -1.0, -1.0], dtype=F64)), atol=0)
+    # Rodrigues' formula for random axes and angles
+    rng = np.random.default_rng(31)
+    for _ in range(20):
+        n = rng.normal(size=3)
+        n /= np.linalg.norm(n)
+        t = rng.uniform(-math.pi, math.pi)
+        q = torch.tensor([[math.cos(t / 2), *(math.sin(t / 2) * n)]], dtype=F64)
+        assert np.allclose(O.quat_to_rot(q)[0].numpy(), _rodrigues(n, t), atol=1e-14)
+
+
+def test_quat_to_rot_is_a_homomorphism():
+    # R(q1 q2) = R(q1) R(q2) with the Hamilton product (w, x, y, z)
+    def hamilton(a, b):
+        w1, x1, y1, z1 = a
+        w2, x2, y2, z2 = b
+        return [w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2]
+    rng = np.random.default_rng(32)
+    for _ in range(10):
+        a, b = rng.normal(size=4), rng.normal(size=4)
+        a /= np.linalg.norm(a)
+        b /= np.linalg.norm(b)
+        Ra = O.quat_to_rot(torch.from_numpy(a[None]))[0]
+        Rb = O.quat_to_rot(torch.from_numpy(b[None]))[0]
+        Rab = O.quat_to_rot(torch.tensor([hamilton(a, b)], dtype=F64))[0]
+        assert torch.allclose(Rab, Ra @ Rb, atol=1e-14)
+        assert torch.allclose(Ra @ Ra.T, torch.eye(3, dtype=F64), atol=1e-14)
+        assert abs(float(torch.linalg.det(Ra)) - 1.0) < 1e-14
+
+
+def test_ewa_anisotropic_rotated_closed_form():
+    # scale (a, b, c) turned a quarter about world z: Sigma = diag(b^2, a^2, c^2).  From the eye
+    # (0, -3, 0) the camera x axis is world x and camera y is world -z, so at the origin
+    # (depth 3) the 2D covariance is (f/3)^2 diag(b^2, c^2) + 0.3 I.
+    f = 70.0
+    cam = hi.look_at((0, -3, 0), (0, 0, 0), f, 64, 64)
+    a, b, c = 0.05, 0.12, 0.2
+    q = torch.tensor([[math.cos(math.pi / 4), 0.0, 0.0, math.sin(math.pi / 4)]], dtype=F64)
+    pr = O.project(torch.zeros(1, 3, dtype=F64), torch.tensor([[a, b, c]], dtype=F64), q, cam)
+    k = (f / 3.0) ** 2
+    assert abs(float(pr["cov2d"][0, 0]) - (k * b * b + 0.3)) < 1e-9
+    assert abs(float(pr["cov2d"][0, 2]) - (k * c * c + 0.3)) < 1e-9
+    assert abs(float(pr["cov2d"][0, 1])) < 1e-9
+    # a quarter turn about world x instead swaps the y and z axes: diag(a^2, c^2, b^2)
+    qx = torch.tensor([[math.cos(math.pi / 4), math.sin(math.pi / 4), 0.0, 0.0]], dtype=F64)
+    pr = O.project(torch.zeros(1, 3, dtype=F64), torch.tensor([[a, b, c]], dtype=F64), qx, cam)
+    assert abs(float(pr["cov2d"][0, 0]) - (k * a * a + 0.3)) < 1e-9
+    assert abs(float(pr["cov2d"][0, 2]) - (k * b * b + 0.3)) < 1e-9
+
+
+def test_camera_center_recovers_the_eye():
+    rng = np.random.default_rng(33)
+    for _ in range(10):
+        eye = rng.uniform(-4, 4, size=3)
+        eye[1] = -abs(eye[1]) - 1.0
+        cam = hi.look_at(eye, rng.uniform(-0.5, 0.5, size=3), 100.0, 64, 48)
+        o = O.camera_center(cam)
+        assert np.allclose(o.numpy(), eye, atol=2e-6 * np.linalg.norm(eye))
+        # the centre maps to the camera-space origin, and the ray origin of every pixel is it
+        t = O.camera_space(o[None], cam)[0]
+        assert float(t.abs().max()) < 2e-6 * np.linalg.norm(eye)
+        ro, _ = O.pixel_rays(torch.tensor([3]), torch.tensor([5]), cam)
+        assert torch.allclose(ro, o, atol=1e-12)
+
+
+def test_view_direction_points_from_the_eye():
+    # the colour decoder's direction for a Gaussian on the optical axis is the viewing direction
+    cam = hi.look_at((1.0, -3.0, 0.5), (0, 0, 0), 70.0, 64, 64)
+    o = O.camera_center(cam)
+    d = -o / o.norm()
+    assert torch.allclose(torch.from_numpy(cam.R[2].astype(np.float64)), d, atol=1e-6)
+
+
+# ------------------------------------------------------------ pair search
+def _all_pairs(px, py, u, v, rx, ry):
+    cx = px.to(F64)[:, None] + 0.5
+    cy = py.to(F64)[:, None] + 0.5
+    m = (torch.abs(cx - u[None]) <= rx[None]) & (torch.abs(cy - v[None]) <= ry[None])
+    a, b = torch.nonzero(m, as_tuple=True)
+    return set(zip(a.tolist(), b.tolist()))
+
+
+@pytest.mark.parametrize("pixels", ["all", "window", "scattered"])
+def test_pair_search_equals_all_pairs(pixels):
+    rng = np.random.default_rng(34)
+    W, H, N = 160, 120, 700
+    u = torch.from_numpy(rng.uniform(-20, W + 20, N))
+    v = torch.from_numpy(rng.uniform(-20, H + 20, N))
+    rx = torch.from_numpy(np.exp(rng.uniform(-1, 3.5, N)))
+    ry = torch.from_numpy(np.exp(rng.uniform(-1, 3.5, N)))
+    rx[:10] = -1.0                               # dropped splats (no box)
+    u[10:20] = torch.floor(u[10:20]) + 0.5        # boxes ending exactly on pixel centres
+    rx[10:20] = torch.round(rx[10:20])
+    if pixels == "all":
+        yy, xx = torch.meshgrid(torch.arange(H), torch.arange(W), indexing="ij")
+        px, py = xx.reshape(-1), yy.reshape(-1)
+    elif pixels == "window":
+        yy, xx = torch.meshgrid(torch.arange(30, 70), torch.arange(50, 110), indexing="ij")
+        px, py = xx.reshape(-1), yy.reshape(-1)
+    else:
+        px = torch.from_numpy(rng.integers(0, W, 500))
+        py = torch.from_numpy(rng.integers(0, H, 500))
+    pi, si = O._pairs_for_pixels(px, py, u, v, rx, ry, chunk=1 << 14)
+    got = list(zip(pi.tolist(), si.tolist()))
+    assert len(got) == len(set(got))
+    assert set(got) == _all_pairs(px, py, u, v, rx, ry)
+
+
+# ------------------------------------------------------------ decision variants / comparison rule
+def test_blend_pixel_flips():
+    al = [0.5, 1.0 / 255.0, 0.3]
+    pw = [-0.1, -2.0, -0.5]
+    rgb = [[1.0, 0.0, 0.0], [0.0, 1.0, 0.0], [0.0, 0.0, 1.0]]
+    C, T = O.blend_pixel(al, pw, rgb)
+    assert math.isclose(T, 0.5 * (1 - 1 / 255) * 0.7, rel_tol=1e-15)
+    C2, T2 = O.blend_pixel(al, pw, rgb, flip_alpha=1)        # the 1/255 splat left out
+    assert math.isclose(T2, 0.5 * 0.7, rel_tol=1e-15) and C2[1] == 0.0
+    assert math.isclose(C2[2], 0.3 * 0.5, rel_tol=1e-15)
+    # early stop: after 0.99 and 0.98, T = 2e-4 and the 0.5 splat brings it to 1e-4 (not below)
+    C, T = O.blend_pixel([0.99, 0.98, 0.5], [-0.1] * 3, rgb)
+    assert math.isclose(T, 1e-4, rel_tol=1e-12) and math.isclose(C[2], 0.5 * 2e-4, rel_tol=1e-12)
+    C3, T3 = O.blend_pixel([0.99, 0.995, 0.5], [-0.1] * 3, rgb)           # 0.01 * 0.005 < 1e-4: stop
+    C4, T4 = O.blend_pixel([0.99, 0.995, 0.5], [-0.1] * 3, rgb, flip_stop=1)
+    assert math.isclose(T3, 0.01, rel_tol=1e-12) and math.isclose(T4, 0.01 * 0.005, rel_tol=1e-12)
+    assert math.isclose(C4[1], 0.995 * 0.01, rel_tol=1e-12)
+
+
+def test_comparison_rule_explains_one_flipped_decision_only():
+    """A float64 'GPU' image made by the oracle itself, with one splat's
+    opacity moved across alpha = 1/255 at one pixel, must be explained by one
+    flipped decision; the same image with an unrelated error must not."""
+    from oracle import parity
+    sc, cam = _tiny_scene(n=60, seed=35)
+    sc.scale_e[:] += 2.0
+    params, fields = O.from_scene(sc)
+    with torch.no_grad():
+        r = O.render_view(params, fields, cam, O.TRAIN, return_stats=True)
+    P_ = r["px"].numel()
+    img = r["rgb"].detach().numpy().copy()
+    # pick a pixel with a contributing pair and rebuild it with that pair's alpha test flipped
+    var = O.decision_variants(r, torch.arange(P_), 1e9, 0.0)
+    k = next(i for i, vv in enumerate(var) if len(vv) > 2 and any(
+        max(abs(a - b) for a, b in zip(x[3], vv[0][3])) > 1e-3 for x in vv[1:]))
+    flipped = next(x for x in var[k][1:] if max(abs(a - b) for a, b in zip(x[3], var[k][0][3])) > 1e-3)
+    good = img.copy()
+    good[k] = flipped[3]
+    res = parity.compare_pixels(good, r, delta_alpha=1e9, delta_T=1e-4)
+    assert res["n_bad"] == 0 and res["n_flip"] == 1 and res["flipped"] == [k]
+    # the same flip is refused when its decision is not near the threshold
+    res = parity.compare_pixels(good, r, delta_alpha=1e-4, delta_T=1e-4)
+    assert res["n_bad"] == 1
+    bad = img.copy()
+    bad[k] += 3e-5
+    res = parity.compare_pixels(bad, r)
+    assert res["n_bad"] == 1 and not res["ok"]
+    assert parity.compare_pixels(img, r)["ok"]
