@@ -214,6 +214,27 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
                               const hyrf_query_out* out, void* ws, size_t ws_bytes,
                               void* stream);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation:
+ * hyrf_query_fields with its scratch (cull flags, their exclusive scan, the
+ * scan's partials) taken from a device array the library holds, instead of a
+ * caller workspace.  Outputs are those of hyrf_query_fields, bit for bit.
+ *  - n must be <= HYRF_QUERY_NOALLOC_MAX_GAUSSIANS; a larger n returns
+ *    HYRF_ERR_CAPACITY with nothing launched.
+ *  - The array, hyrf_query_noalloc_scratch_bytes() bytes (about 32 MiB), is
+ *    held by every GPU the library runs on until the process ends.  The first
+ *    call on a device looks up its address there once (the calling thread's
+ *    current device must be the device of `stream`); no call allocates or
+ *    frees memory.
+ *  - Every call on one GPU uses that GPU's one array: calls that overlap on
+ *    one GPU (two streams, two threads) race and must be serialised by the
+ *    caller.  Nothing in it needs clearing between calls. */
+#define HYRF_QUERY_NOALLOC_MAX_GAUSSIANS (1 << 22)
+size_t hyrf_query_noalloc_scratch_bytes(void);
+hyrf_status hyrf_query_fields_noalloc(const hyrf_fields* fields, const hyrf_gaussians* g,
+                                      const hyrf_camera* cams, int32_t n_views,
+                                      const hyrf_query_out* out, void* stream);
+
 /* EWA projection of every surviving Gaussian into every view (3DGS
  * rasterizer, Sec. 3.1): 2D covariance J W Sigma W^T J^T + 0.3 I, conic,
  * centre, float32 depth key, and a conservative tile rectangle holding every

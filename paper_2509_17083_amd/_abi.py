@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(_PKG, "lib", "libhyrf.so")
 HYRF_OK, HYRF_ERR_INVALID_ARGUMENT, HYRF_ERR_UNSUPPORTED, HYRF_ERR_CAPACITY, HYRF_ERR_LAUNCH = range(5)
 HYRF_F32, HYRF_F16, HYRF_BF16, HYRF_U8 = 0, 1, 2, 3
 HYRF_RENDER, HYRF_TRAIN = 0, 1
+HYRF_QUERY_NOALLOC_MAX_GAUSSIANS = 1 << 22
 TILE = 16
 MAX_VIEWS = 8
 
@@ -73,6 +74,9 @@ class hyrf_fwd_state(C.Structure):
 EXPORTS = {
     "hyrf_query_fields": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians), C.POINTER(hyrf_camera),
                                     C.c_int32, C.POINTER(hyrf_query_out), P, C.c_size_t, P]),
+    "hyrf_query_fields_noalloc": (C.c_int, [C.POINTER(hyrf_fields), C.POINTER(hyrf_gaussians),
+                                            C.POINTER(hyrf_camera), C.c_int32, C.POINTER(hyrf_query_out), P]),
+    "hyrf_query_noalloc_scratch_bytes": (C.c_size_t, []),
     "hyrf_project": (C.c_int, [C.POINTER(hyrf_gaussians), C.POINTER(hyrf_query_out), C.POINTER(hyrf_camera),
                                C.c_int32, C.POINTER(hyrf_splats), P]),
     "hyrf_bin_sort": (C.c_int, [C.POINTER(hyrf_splats), C.POINTER(hyrf_camera), C.c_int32, C.c_int64,

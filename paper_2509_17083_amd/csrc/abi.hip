@@ -5,6 +5,7 @@
 #include <stdarg.h>
 #include <stdio.h>
 
+#include <mutex>
 #include <string>
 
 #include "backward.h"
@@ -154,18 +155,8 @@ size_t query_ws(int n, uint32_t** flag, uint32_t** pos, uint32_t** temp, void* b
   return c.off;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char* hyrf_last_error(void) { return g_err.c_str(); }
-const char* hyrf_version(void) { return "hyrf-gfx950 0.1"; }
-
-size_t hyrf_query_workspace_bytes(int32_t n) { return query_ws(n, nullptr, nullptr, nullptr, nullptr); }
-
-hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g,
-                              const hyrf_camera* cams, int32_t n_views, const hyrf_query_out* out,
-                              void* ws, size_t ws_bytes, void* stream) {
+hyrf_status check_query(const hyrf_fields* fields, const hyrf_gaussians* g, const hyrf_camera* cams,
+                        int32_t n_views, const hyrf_query_out* out) {
   hyrf_status s;
   if ((s = check_fields(fields)) != HYRF_OK) return s;
   if ((s = check_gauss(g)) != HYRF_OK) return s;
@@ -173,9 +164,13 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
   REQ(out && out->vis_count && out->vis_idx, "query output: vis_count / vis_idx is NULL");
   REQ(g->n == 0 || (out->opacity && out->scale && out->quat && out->rgb), "query output: a property array is NULL");
   REQ((out->feat_geo == nullptr) == (out->feat_rad == nullptr), "feat_geo and feat_rad must both be set or both NULL");
-  const size_t need = hyrf_query_workspace_bytes(g->n);
-  REQ(ws && ws_bytes >= need, "query workspace too small: %zu < %zu bytes", ws_bytes, need);
-  hipStream_t st = (hipStream_t)stream;
+  return HYRF_OK;
+}
+
+// Pre-cull, compaction and field query of validated arguments; `ws` holds
+// query_ws(g->n) bytes (cull flags, their exclusive scan, scan partials).
+void launch_query_all(const hyrf_fields* fields, const hyrf_gaussians* g, const hyrf_camera* cams,
+                      int32_t n_views, const hyrf_query_out* out, void* ws, hipStream_t st) {
   uint32_t *flag, *pos, *temp;
   query_ws(g->n, &flag, &pos, &temp, ws);
   const Cams cc = make_cams(cams, n_views);
@@ -207,6 +202,25 @@ hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g
     launch_query(fields->levels, fields->hidden, fields->n_hidden, fields->table_dtype,
                  fields->mlp_dtype == HYRF_BF16, a, g->n, st);
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* hyrf_last_error(void) { return g_err.c_str(); }
+const char* hyrf_version(void) { return "hyrf-gfx950 0.1"; }
+
+size_t hyrf_query_workspace_bytes(int32_t n) { return query_ws(n, nullptr, nullptr, nullptr, nullptr); }
+
+hyrf_status hyrf_query_fields(const hyrf_fields* fields, const hyrf_gaussians* g,
+                              const hyrf_camera* cams, int32_t n_views, const hyrf_query_out* out,
+                              void* ws, size_t ws_bytes, void* stream) {
+  hyrf_status s;
+  if ((s = check_query(fields, g, cams, n_views, out)) != HYRF_OK) return s;
+  const size_t need = hyrf_query_workspace_bytes(g->n);
+  REQ(ws && ws_bytes >= need, "query workspace too small: %zu < %zu bytes", ws_bytes, need);
+  launch_query_all(fields, g, cams, n_views, out, ws, (hipStream_t)stream);
   return check_launch();
 }
 
@@ -639,6 +653,88 @@ hyrf_status hyrf_spatial_order(const hyrf_fields* fields, const float* pos, int3
     g.inv_half[d] = fields->aabb_inv_half[d];
   }
   launch_order(pos, n, g, perm, ws, (hipStream_t)stream);
+  return check_launch();
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------- query without a workspace
+// The query's scratch (cull flags, their exclusive scan and the scan's
+// per-workgroup partials) in a device array that the library holds, for
+// callers that cannot allocate.  Each GPU that loads the library holds its
+// own copy of the array until the process ends; host code reaches it only
+// through the address hipGetSymbolAddress returns on that device (the
+// array's name on the host is a stand-in, not a device address).
+namespace {
+
+constexpr int64_t NOALLOC_MAX_N = HYRF_QUERY_NOALLOC_MAX_GAUSSIANS;
+
+constexpr size_t scan_temp_elems_bound(int64_t n) {
+  size_t s = 0;
+  while (n > SCAN_ITEMS) {
+    const int64_t nb = (n + SCAN_ITEMS - 1) / SCAN_ITEMS;
+    s += (size_t)nb;
+    n = nb;
+  }
+  return s + 1;
+}
+
+// query_ws of the largest accepted n: two arrays of n words, each start
+// rounded up to 256 bytes (64 words), then the scan partials
+constexpr size_t NOALLOC_WORDS = 2 * (size_t)NOALLOC_MAX_N + 64 + scan_temp_elems_bound(NOALLOC_MAX_N);
+
+}  // namespace
+
+static __device__ __align__(256) uint32_t scratch[NOALLOC_WORDS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+// Device address of `scratch` on the calling thread's current device,
+// looked up once per device.
+hyrf_status scratch_address(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HYRF_ERR_LAUNCH, "hipGetDevice failed: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(HYRF_ERR_UNSUPPORTED, "device %d outside the %d devices the scratch table covers", dev,
+                NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HYRF_ERR_LAUNCH, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_dev[dev] = ptr;
+  }
+  *out = g_scratch_dev[dev];
+  return HYRF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t hyrf_query_noalloc_scratch_bytes(void) { return sizeof(scratch); }
+
+hyrf_status hyrf_query_fields_noalloc(const hyrf_fields* fields, const hyrf_gaussians* g,
+                                      const hyrf_camera* cams, int32_t n_views, const hyrf_query_out* out,
+                                      void* stream) {
+  hyrf_status s;
+  if ((s = check_query(fields, g, cams, n_views, out)) != HYRF_OK) return s;
+  if (g->n > NOALLOC_MAX_N)
+    return fail(HYRF_ERR_CAPACITY, "hyrf_query_fields_noalloc: n = %d exceeds the %lld Gaussians its scratch holds",
+                g->n, (long long)NOALLOC_MAX_N);
+  if (query_ws(g->n, nullptr, nullptr, nullptr, nullptr) > sizeof(scratch))
+    return fail(HYRF_ERR_CAPACITY, "hyrf_query_fields_noalloc: scratch too small for n = %d", g->n);
+  void* ptr = nullptr;
+  if ((s = scratch_address(&ptr)) != HYRF_OK) return s;
+  // nothing in the scratch needs to start at zero: the cull writes every
+  // flag, the scan every position and partial it reads
+  launch_query_all(fields, g, cams, n_views, out, ptr, (hipStream_t)stream);
   return check_launch();
 }
 

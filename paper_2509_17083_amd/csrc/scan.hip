@@ -61,6 +61,9 @@ __global__ __launch_bounds__(NT) void k_scan_down(const uint32_t* in, uint32_t* 
   }
   if (total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = b + tot;
 }
+__global__ void k_store_zero(uint32_t* p) {
+  if (threadIdx.x == 0) *p = 0u;
+}
 }  // namespace
 
 size_t scan_temp_elems(int64_t n) {
@@ -76,7 +79,8 @@ size_t scan_temp_elems(int64_t n) {
 void scan_exclusive_u32(const uint32_t* in, uint32_t* out, int64_t n, uint32_t* temp,
                         uint32_t* total, hipStream_t st) {
   if (n <= 0) {
-    if (total) hipMemsetAsync(total, 0, sizeof(uint32_t), st);
+    // a kernel, not a memset node, so that the call can sit in a captured graph
+    if (total) k_store_zero<<<1, 64, 0, st>>>(total);
     return;
   }
   if (n <= SCAN_ITEMS) {

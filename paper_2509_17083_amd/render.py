@@ -215,11 +215,8 @@ class ForwardState:
     c: Dict[str, object] = field(default_factory=dict)   # ctypes structs kept alive
 
 
-def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False,
-                 ws: Optional[Workspace] = None):
-    lib = A.load()
-    ws = ws or Workspace()
-    n, V, L = scene.n, len(cams), scene.levels
+def _query_outputs(scene: DeviceScene, V: int, mode: int, debug_index: bool):
+    n, L = scene.n, scene.levels
     dev = scene.pos.device
     q = dict(vis_count=torch.empty(1, dtype=torch.int32, device=dev),
              vis_idx=torch.empty(max(n, 1), dtype=torch.int32, device=dev),
@@ -234,11 +231,32 @@ def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool
     out = A.hyrf_query_out(*[q[k].data_ptr() if k in q else None for k in
                              ("vis_count", "vis_idx", "opacity", "scale", "quat", "rgb", "feat_geo",
                               "feat_rad", "dbg_index", "feat_jac")])
+    return q, out
+
+
+def query_fields(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False,
+                 ws: Optional[Workspace] = None):
+    lib = A.load()
+    ws = ws or Workspace()
+    q, out = _query_outputs(scene, len(cams), mode, debug_index)
     f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
-    nb = lib.hyrf_query_workspace_bytes(n)
+    nb = lib.hyrf_query_workspace_bytes(scene.n)
     w = ws.get("query", nb)
-    A.check("hyrf_query_fields", lib.hyrf_query_fields(C.byref(f), C.byref(g), cc, V, C.byref(out),
+    A.check("hyrf_query_fields", lib.hyrf_query_fields(C.byref(f), C.byref(g), cc, len(cams), C.byref(out),
                                                        _p(w), w.numel(), _stream()))
+    return q, out
+
+
+def query_fields_noalloc(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False,
+                         outputs=None):
+    """hyrf_query_fields_noalloc: the same query with the library's own
+    scratch instead of a workspace.  `outputs` = (q, out) from an earlier call
+    to reuse its buffers (then this call allocates nothing at all)."""
+    lib = A.load()
+    q, out = outputs if outputs is not None else _query_outputs(scene, len(cams), mode, debug_index)
+    f, g, cc = scene.c_fields(), scene.c_gauss(), c_cameras(cams)
+    A.check("hyrf_query_fields_noalloc", lib.hyrf_query_fields_noalloc(C.byref(f), C.byref(g), cc, len(cams),
+                                                                       C.byref(out), _stream()))
     return q, out
 
 
