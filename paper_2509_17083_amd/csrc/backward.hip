@@ -328,23 +328,71 @@ struct Dec {
     if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC, NWV>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
     else mlp_backward<Sh, COL, S1, ACC, NWV>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
   }
+  // Colour decoder over several views with its input [f_rad ; PE(d_v)]
+  // (Eq. 6): the first layer's product with the radiance features (lane
+  // k-steps [0, FPL)) is formed once per point (col_first), each view adds
+  // its direction part (col_fwd_rest); in the adjoint each view handles the
+  // direction columns of the first layer (col_bwd_view) and sums its
+  // first-layer output gradient, whose product with the features
+  // (col_bwd_features: their dW tiles and dL/df_rad) is formed once.
+  static constexpr int SPLIT = Sh::FPL;
+  static constexpr int TIF = 2 * Sh::L / 16;   // first-layer input tiles of the features
+  static_assert((2 * Sh::L) % 16 == 0 && SPLIT % (BF ? 8 : 4) == 0, "feature columns must fill whole tiles");
+  static __device__ void col_first(const void* W, const float (&x)[SC], v4f (&acc)[Sh::NT], int lane) {
+    if constexpr (BF) mlp_first_part_bf16<Sh, SC, SPLIT>((const __bf16*)W, x, acc, lane);
+    else mlp_first_part<Sh, SC, SPLIT>((const float*)W, x, acc, lane);
+  }
+  static __device__ void col_fwd_rest(const void* W, const float (&x)[SC], v4f (&acc)[Sh::NT],
+                                      float (&h)[Sh::NH][Sh::S_HID], v4f& o, int lane) {
+    if constexpr (BF) mlp_forward_keep_rest_bf16<Sh, SC, SPLIT>((const __bf16*)W, x, acc, h, o, lane);
+    else mlp_forward_keep_rest<Sh, SC, SPLIT>((const float*)W, x, acc, h, o, lane);
+  }
+  template <int ACC, int NWV>
+  static __device__ void col_bwd_view(const void* W, const float (&x)[SC], const float (&h)[Sh::NH][Sh::S_HID],
+                                      v4f dout, float (&dx)[SC], float (&dh_sum)[Sh::S_HID], float* Xs, float* Ys,
+                                      v4f (&acc)[ACC], int w, int lane) {
+    using B = BwdShape<Sh>;
+    float dh[Sh::S_HID];
+    if constexpr (BF) {
+      const __bf16* W1 = mlp_backward_upper_bf16<Sh, true, ACC, NWV>((const __bf16*)W, h, dout, dh, Xs, Ys, acc, w, lane);
+      mlp_backward_first_bf16<Sh, true, SC, SPLIT, SC, TIF, B::TI_COL1, ACC, NWV>(W1, x, dh, dx, Xs, Ys, acc, w, lane);
+    } else {
+      const float* W1 = mlp_backward_upper<Sh, true, ACC, NWV>((const float*)W, h, dout, dh, Xs, Ys, acc, w, lane);
+      mlp_backward_first<Sh, true, SC, SPLIT, SC, TIF, B::TI_COL1, ACC, NWV>(W1, x, dh, dx, Xs, Ys, acc, w, lane);
+    }
+#pragma unroll
+    for (int k = 0; k < Sh::S_HID; ++k) dh_sum[k] += dh[k];
+  }
+  template <int ACC, int NWV>
+  static __device__ void col_bwd_features(const void* W, const float (&x)[SC], const float (&dh_sum)[Sh::S_HID],
+                                          float (&dx)[SC], float* Xs, float* Ys, v4f (&acc)[ACC], int w, int lane) {
+    // the first layer's adjoint operands follow the output and hidden layers'
+    if constexpr (BF) {
+      const __bf16* W1 = (const __bf16*)W + Sh::NT * 8 * 64 + (Sh::NH - 1) * Sh::NT * Sh::S_HID * 64;
+      mlp_backward_first_bf16<Sh, true, SC, 0, SPLIT, 0, TIF, ACC, NWV>(W1, x, dh_sum, dx, Xs, Ys, acc, w, lane);
+    } else {
+      const float* W1 = (const float*)W + Sh::NT * 4 * 64 + (Sh::NH - 1) * Sh::NT * Sh::S_HID * 64;
+      mlp_backward_first<Sh, true, SC, 0, SPLIT, 0, TIF, ACC, NWV>(W1, x, dh_sum, dx, Xs, Ys, acc, w, lane);
+    }
+  }
 };
 
 // Write the dW tiles of one layer (tile ids ID0 ..) owned by this wave.
-template <int ID0, int TO, int TI, int ACC, int NWV>
+template <int ID0, int TO, int TI, int ACC, int NWV, bool ITMAJ = false>
 __device__ __forceinline__ void write_dw_layer(float* dst, int rows, int in, const v4f (&acc)[ACC], int w, int lane) {
   const int j = lane & 15, g = lane >> 4;
+  static_for<0, TO * TI>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    constexpr int id = ID0 + t;
+    constexpr int ot = tile_ot<TO, TI, ITMAJ>(t), it = tile_it<TO, TI, ITMAJ>(t);
+    if (id % NWV == w) {
 #pragma unroll
-  for (int t = 0; t < TO * TI; ++t) {
-    const int id = ID0 + t;
-    if (id % NWV != w) continue;
-    const int ot = t / TI, it = t % TI;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * ot + 4 * g + r, col = 16 * it + j;
-      if (row < rows && col < in) dst[row * in + col] = acc[id / NWV][r];
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * ot + 4 * g + r, col = 16 * it + j;
+        if (row < rows && col < in) dst[row * in + col] = acc[id / NWV][r];
+      }
     }
-  }
+  });
 }
 
 template <class Sh, int ACC, int NWV>
@@ -365,7 +413,7 @@ __device__ void write_dw(float* part, const v4f (&acc)[ACC], int w, int lane) {
   dst += HYRF_GEO_OUT * Sh::HID;
   // colour MLP
   constexpr int C0 = B::TILES_GEO;
-  write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC, NWV>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
+  write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC, NWV, true>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
   dst += Sh::HID * Sh::IN_COL;
   constexpr int C1 = C0 + Sh::NT * B::TI_COL1;
   if constexpr (Sh::NH == 2) {
@@ -764,8 +812,21 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         for (int s = 0; s < Sh::FPL; ++s) fr[s] = 0.f;
       }
     }
-    // ---- colour decoder adjoint, once per view (one pass in ray mode)
+    // ---- colour decoder adjoint, once per view (one pass in ray mode).
+    // With several views the first layer's radiance-feature part is shared
+    // (Eq. 6): formed once forward, its adjoint once after the views.
     const int nviews = RAY ? 1 : V;
+    const bool shared = !RAY && V > 1;
+    v4f col1[Sh::NT];
+    float dh_sum[Sh::S_HID];
+    float x1f[D::SC];
+#pragma unroll
+    for (int s = 0; s < D::SC; ++s) x1f[s] = (valid && s < Sh::FPL) ? fr[s] : 0.f;
+    if (shared) {
+      D::col_first(s_wf_col, x1f, col1, lane);
+#pragma unroll
+      for (int k = 0; k < Sh::S_HID; ++k) dh_sum[k] = 0.f;
+    }
     for (int v = 0; v < nviews; ++v) {
       float dir[3];
       float inv_len = 0.f;
@@ -786,7 +847,14 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         x1c[s] = !valid ? 0.f : (s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f));
       float hc[Sh::NH][Sh::S_HID];
       v4f oc4;
-      D::template fwd<D::SC>(s_wf_col, x1c, hc, oc4, lane);
+      if (shared) {
+        v4f acc1[Sh::NT];
+#pragma unroll
+        for (int t = 0; t < Sh::NT; ++t) acc1[t] = col1[t];
+        D::col_fwd_rest(s_wf_col, x1c, acc1, hc, oc4, lane);
+      } else {
+        D::template fwd<D::SC>(s_wf_col, x1c, hc, oc4, lane);
+      }
       v4f dc = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         if constexpr (!RAY) {
@@ -808,9 +876,13 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       // the forward above needs no LDS staging, so the wait sits just
       // before the adjoint's first staging write
       if constexpr (RAY) __syncthreads();
-      D::template bwd<true, D::SC, ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+      if (shared) {
+        D::template col_bwd_view<ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, dh_sum, Xs, Ys, accW, w, lane);
+      } else {
+        D::template bwd<true, D::SC, ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
-      for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
+        for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
+      }
       if constexpr (!RAY) {
         // PE of octave g: d sin(a d)/dd = a cos(a d), d cos(a d)/dd = -a sin(a d)
         const float af = 3.14159265358979323846f * (float)(1 << g);
@@ -821,6 +893,12 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
 #pragma unroll
         for (int k = 0; k < 3; ++k) dp_dir[k] += (dd[k] - dir[k] * dot) * inv_len;
       }
+    }
+    if (shared) {
+      float dxf[D::SC];
+      D::template col_bwd_features<ACC, NWV>(s_wb_col, x1f, dh_sum, dxf, Xs, Ys, accW, w, lane);
+#pragma unroll
+      for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxf[s];
     }
     if constexpr (!RAY) {
       // decoder-side results: feature gradients (canonical order) for the

@@ -99,25 +99,38 @@ __device__ void load_mlp_lds(float* lds, const float* __restrict__ W, bool colou
   permute_mlp_fwd<Sh>(lds, W, colour, threadIdx.x, blockDim.x);
 }
 
-// One layer: acc[ot] = sum_s W(ot, s) * x[s]   (x: this lane's B operands).
+// Output tiles [OT0, OT1) of one layer of S k-steps, accumulated over its
+// k-steps [K0, K1): acc[ot - OT0] += sum_s W(ot, s) * x[s]  (x: this lane's
+// B operands).  Per accumulator the MFMA sequence is that of the whole
+// layer restricted to the range, so splitting a layer's k-steps into
+// consecutive ranges gives the same bits as one pass.
+template <int OT0, int OT1, int S, int K0, int K1>
+__device__ __forceinline__ void mfma_accum(const float* __restrict__ Wl, const float (&x)[S],
+                                           v4f (&acc)[OT1 - OT0], int lane) {
+  static_assert(K0 % 4 == 0 && K1 % 4 == 0 && 0 <= K0 && K0 <= K1 && K1 <= S, "k-step range");
+#pragma unroll
+  for (int sq = K0 / 4; sq < K1 / 4; ++sq) {
+#pragma unroll
+    for (int ot = OT0; ot < OT1; ++ot) {
+      const float4 w = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq) * 64 + lane) * 4);
+      v4f& c = acc[ot - OT0];
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, x[4 * sq + 0], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, x[4 * sq + 1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, x[4 * sq + 2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, x[4 * sq + 3], c, 0, 0, 0);
+    }
+    // keep the weight reads of one k-quad in flight at a time (register budget)
+    asm volatile("" ::: "memory");
+  }
+}
+
+// One layer: acc[ot] = sum_s W(ot, s) * x[s].
 template <int NTO, int S>
 __device__ __forceinline__ void mfma_layer(const float* __restrict__ Wl, const float (&x)[S],
                                            v4f (&acc)[NTO], int lane) {
 #pragma unroll
   for (int ot = 0; ot < NTO; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int sq = 0; sq < S / 4; ++sq) {
-#pragma unroll
-    for (int ot = 0; ot < NTO; ++ot) {
-      const float4 w = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq) * 64 + lane) * 4);
-      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, x[4 * sq + 0], acc[ot], 0, 0, 0);
-      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, x[4 * sq + 1], acc[ot], 0, 0, 0);
-      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, x[4 * sq + 2], acc[ot], 0, 0, 0);
-      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, x[4 * sq + 3], acc[ot], 0, 0, 0);
-    }
-    // keep the weight reads of one k-quad in flight at a time (register budget)
-    asm volatile("" ::: "memory");
-  }
+  mfma_accum<0, NTO, S, 0, S>(Wl, x, acc, lane);
 }
 
 template <int NTO>
@@ -128,17 +141,14 @@ __device__ __forceinline__ void relu_to_inputs(const v4f (&acc)[NTO], float (&x)
     for (int r = 0; r < 4; ++r) x[4 * b + r] = fmaxf(acc[b][r], 0.f);
 }
 
-// Whole MLP from first-layer inputs x1 to the 16-row output tile `out`
-// (lane holds rows 4g..4g+3).  Optionally keeps the hidden activations
-// (pre-ReLU) for the backward.
-template <class Sh, int S1>
-__device__ __forceinline__ void mlp_forward(const float* __restrict__ Wlds, const float (&x1)[S1],
-                                            v4f& out, int lane) {
-  v4f acc[Sh::NT];
-  mfma_layer<Sh::NT, S1>(Wlds, x1, acc, lane);
-  const float* W = Wlds + Sh::NT * S1 * 64;
+// Hidden and output layers from the first layer's pre-activations `acc`;
+// W: the weights that follow the first layer's.
+template <class Sh>
+__device__ __forceinline__ void mlp_tail(const float* __restrict__ W, const v4f (&acc1)[Sh::NT], v4f& out,
+                                         int lane) {
   float h[Sh::S_HID];
-  relu_to_inputs<Sh::NT>(acc, h);
+  relu_to_inputs<Sh::NT>(acc1, h);
+  v4f acc[Sh::NT];
 #pragma unroll
   for (int k = 1; k < Sh::NH; ++k) {
     mfma_layer<Sh::NT, Sh::S_HID>(W, h, acc, lane);
@@ -148,6 +158,36 @@ __device__ __forceinline__ void mlp_forward(const float* __restrict__ Wlds, cons
   v4f o[1];
   mfma_layer<1, Sh::S_HID>(W, h, o, lane);
   out = o[0];
+}
+
+// Whole MLP from first-layer inputs x1 to the 16-row output tile `out`
+// (lane holds rows 4g..4g+3).
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward(const float* __restrict__ Wlds, const float (&x1)[S1],
+                                            v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer<Sh::NT, S1>(Wlds, x1, acc, lane);
+  mlp_tail<Sh>(Wlds + Sh::NT * S1 * 64, acc, out, lane);
+}
+
+// The colour decoder over several views of one point (Eq. 6): its input is
+// [f_rad ; PE(d_v)], so the first layer's product with the radiance features
+// (k-steps [0, SPLIT)) does not depend on the view.  mlp_first_part forms it
+// once; mlp_forward_rest adds the view's direction part (k-steps [SPLIT, S1))
+// to a copy and runs the remaining layers.  Same bits as mlp_forward.
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_first_part(const float* __restrict__ Wlds, const float (&x1)[S1],
+                                               v4f (&acc)[Sh::NT], int lane) {
+#pragma unroll
+  for (int ot = 0; ot < Sh::NT; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
+  mfma_accum<0, Sh::NT, S1, 0, SPLIT>(Wlds, x1, acc, lane);
+}
+
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_forward_rest(const float* __restrict__ Wlds, const float (&x1)[S1],
+                                                 v4f (&acc)[Sh::NT], v4f& out, int lane) {
+  mfma_accum<0, Sh::NT, S1, SPLIT, S1>(Wlds, x1, acc, lane);
+  mlp_tail<Sh>(Wlds + Sh::NT * S1 * 64, acc, out, lane);
 }
 
 
@@ -188,34 +228,38 @@ __device__ void permute_mlp_fwd_bf16(__bf16* dst, const float* __restrict__ W, b
   }
 }
 
-template <int NTO, int S>
-__device__ __forceinline__ void mfma_layer_bf16(const __bf16* __restrict__ Wl, const float (&x)[S],
-                                                v4f (&acc)[NTO], int lane) {
-  static_assert(S % 8 == 0, "bf16 layer width");
+template <int OT0, int OT1, int S, int K0, int K1>
+__device__ __forceinline__ void mfma_accum_bf16(const __bf16* __restrict__ Wl, const float (&x)[S],
+                                                v4f (&acc)[OT1 - OT0], int lane) {
+  static_assert(S % 8 == 0 && K0 % 8 == 0 && K1 % 8 == 0 && 0 <= K0 && K0 <= K1 && K1 <= S, "bf16 k-step range");
 #pragma unroll
-  for (int ot = 0; ot < NTO; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int q = 0; q < S / 8; ++q) {
+  for (int q = K0 / 8; q < K1 / 8; ++q) {
     v8bf b;
 #pragma unroll
     for (int e = 0; e < 8; ++e) b[e] = (__bf16)x[8 * q + e];
 #pragma unroll
-    for (int ot = 0; ot < NTO; ++ot) {
+    for (int ot = OT0; ot < OT1; ++ot) {
       const v8bf w = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + q) * 64 + lane) * 8);
-      acc[ot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, acc[ot], 0, 0, 0);
+      acc[ot - OT0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, acc[ot - OT0], 0, 0, 0);
     }
     asm volatile("" ::: "memory");
   }
 }
 
-template <class Sh, int S1>
-__device__ __forceinline__ void mlp_forward_bf16(const __bf16* __restrict__ Wlds, const float (&x1)[S1],
-                                                 v4f& out, int lane) {
-  v4f acc[Sh::NT];
-  mfma_layer_bf16<Sh::NT, S1>(Wlds, x1, acc, lane);
-  const __bf16* W = Wlds + Sh::NT * S1 * 64;
+template <int NTO, int S>
+__device__ __forceinline__ void mfma_layer_bf16(const __bf16* __restrict__ Wl, const float (&x)[S],
+                                                v4f (&acc)[NTO], int lane) {
+#pragma unroll
+  for (int ot = 0; ot < NTO; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
+  mfma_accum_bf16<0, NTO, S, 0, S>(Wl, x, acc, lane);
+}
+
+template <class Sh>
+__device__ __forceinline__ void mlp_tail_bf16(const __bf16* __restrict__ W, const v4f (&acc1)[Sh::NT], v4f& out,
+                                              int lane) {
   float h[Sh::S_HID];
-  relu_to_inputs<Sh::NT>(acc, h);
+  relu_to_inputs<Sh::NT>(acc1, h);
+  v4f acc[Sh::NT];
 #pragma unroll
   for (int k = 1; k < Sh::NH; ++k) {
     mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, h, acc, lane);
@@ -225,6 +269,29 @@ __device__ __forceinline__ void mlp_forward_bf16(const __bf16* __restrict__ Wlds
   v4f o[1];
   mfma_layer_bf16<1, Sh::S_HID>(W, h, o, lane);
   out = o[0];
+}
+
+template <class Sh, int S1>
+__device__ __forceinline__ void mlp_forward_bf16(const __bf16* __restrict__ Wlds, const float (&x1)[S1],
+                                                 v4f& out, int lane) {
+  v4f acc[Sh::NT];
+  mfma_layer_bf16<Sh::NT, S1>(Wlds, x1, acc, lane);
+  mlp_tail_bf16<Sh>(Wlds + Sh::NT * S1 * 64, acc, out, lane);
+}
+
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_first_part_bf16(const __bf16* __restrict__ Wlds, const float (&x1)[S1],
+                                                    v4f (&acc)[Sh::NT], int lane) {
+#pragma unroll
+  for (int ot = 0; ot < Sh::NT; ++ot) acc[ot] = v4f{0.f, 0.f, 0.f, 0.f};
+  mfma_accum_bf16<0, Sh::NT, S1, 0, SPLIT>(Wlds, x1, acc, lane);
+}
+
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_forward_rest_bf16(const __bf16* __restrict__ Wlds, const float (&x1)[S1],
+                                                      v4f (&acc)[Sh::NT], v4f& out, int lane) {
+  mfma_accum_bf16<0, Sh::NT, S1, SPLIT, S1>(Wlds, x1, acc, lane);
+  mlp_tail_bf16<Sh>(Wlds + Sh::NT * S1 * 64, acc, out, lane);
 }
 
 // Table entry loads: FP32 pairs or FP16 pairs widened to FP32.

@@ -11,6 +11,8 @@
 //    every wave accumulates a fixed subset of the 16x16 dW tiles over all
 //    staged points in registers, across every round of the persistent loop.
 #pragma once
+#include <type_traits>
+
 #include "field.h"
 
 namespace hyrf {
@@ -106,76 +108,135 @@ __device__ __forceinline__ void mlp_forward_keep(const float* __restrict__ Wf, c
   out = o[0];
 }
 
+// The same from the first layer's pre-activations (the colour decoder with
+// its view-independent part formed once: mlp_first_part, field.h).
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_forward_keep_rest(const float* __restrict__ Wf, const float (&x1)[S1],
+                                                      v4f (&acc)[Sh::NT], float (&h)[Sh::NH][Sh::S_HID],
+                                                      v4f& out, int lane) {
+  mfma_accum<0, Sh::NT, S1, SPLIT, S1>(Wf, x1, acc, lane);
+  const float* W = Wf + Sh::NT * S1 * 64;
+  relu_to_inputs<Sh::NT>(acc, h[0]);
+  v4f a2[Sh::NT];
+#pragma unroll
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer<Sh::NT, Sh::S_HID>(W, h[k - 1], a2, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(a2, h[k]);
+  }
+  v4f o[1];
+  mfma_layer<1, Sh::S_HID>(W, h[Sh::NH - 1], o, lane);
+  out = o[0];
+}
+
 __device__ __forceinline__ int swz(int row, int col) { return row * STAGE_W + (col ^ ((row & 1) << 4)); }
 
-// Accumulate the dW tiles of one layer from the staged [point][feature]
-// arrays: tile (ot, it) += sum_p Y[p][16 ot + i] X[p][16 it + j].
-// Tile ids TB .. TB + TO*TI - 1; wave w owns ids with id % NWV == w.
+__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
+
+// Tile t of a layer with TO output and TI input tiles is (ot, it).  The
+// colour decoder's first layer numbers its tiles input-major (ITMAJ), so that
+// the tiles of its feature columns and those of its direction columns, when
+// accumulated apart, each spread evenly over the waves.
+template <int TO, int TI, bool ITMAJ>
+__host__ __device__ constexpr int tile_ot(int t) { return ITMAJ ? t % TO : t / TI; }
+template <int TO, int TI, bool ITMAJ>
+__host__ __device__ constexpr int tile_it(int t) { return ITMAJ ? t / TO : t % TI; }
+
+// Compile-time loop: f(std::integral_constant<int, i>) for i in [I0, I1), so
+// that register-array indices derived from i stay constants (a runtime index
+// would move the array to scratch memory).
+template <int I0, int I1, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I0 < I1) {
+    f(std::integral_constant<int, I0>{});
+    static_for<I0 + 1, I1>(f);
+  }
+}
+
+// Accumulate the dW tiles of one layer whose input tile lies in [IT0, IT1)
+// from the staged [point][feature] arrays: tile (ot, it) += sum_p
+// Y[p][16 ot + i] X[p][16 it + j].  Tile ids TB .. TB + TO*TI - 1; wave w
+// owns ids with id % NWV == w.
+template <int TB, int TO, int TI, bool ITMAJ, int IT0, int IT1, int ACC, int NWV>
+__device__ __forceinline__ void dw_tiles_range(const float* Xs, const float* Ys, v4f (&acc)[ACC], int w, int lane) {
+  const int kk = lane >> 4, i = lane & 15;
+  static_for<0, TO * TI>([&](auto tc) {
+    constexpr int t = decltype(tc)::value;
+    constexpr int ot = tile_ot<TO, TI, ITMAJ>(t), it = tile_it<TO, TI, ITMAJ>(t);
+    constexpr int id = TB + t;
+    if constexpr (it >= IT0 && it < IT1) {
+      if (id % NWV == w) {
+        v4f c = acc[id / NWV];
+        // k runs over the staged points, 4 per MFMA, UB MFMAs per unrolled
+        // block (fewer with 8 waves, whose registers are capped at 256)
+        constexpr int KS = NWV * 16 / 4;
+        constexpr int UB = NWV >= 8 ? 1 : 8;
+        static_assert(KS % UB == 0, "staged points per round");
+        for (int s0 = 0; s0 < KS; s0 += UB) {
+#pragma unroll
+          for (int u = 0; u < UB; ++u) {
+            const int p = 4 * (s0 + u) + kk;
+            const float av = Ys[swz(p, 16 * ot + i)];
+            const float bv = Xs[swz(p, 16 * it + i)];
+            c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+          }
+        }
+        acc[id / NWV] = c;
+      }
+    }
+  });
+}
+
 template <int TB, int TO, int TI, int ACC, int NWV>
 __device__ __forceinline__ void dw_tiles(const float* Xs, const float* Ys, v4f (&acc)[ACC], int w, int lane) {
-  const int kk = lane >> 4, i = lane & 15;
-#pragma unroll
-  for (int t = 0; t < TO * TI; ++t) {
-    const int id = TB + t;
-    if (id % NWV != w) continue;
-    const int ot = t / TI, it = t % TI;
-    v4f c = acc[id / NWV];
-#pragma unroll 8
-    for (int s = 0; s < NWV * 16 / 4; ++s) {
-      const int p = 4 * s + kk;
-      const float av = Ys[swz(p, 16 * ot + i)];
-      const float bv = Xs[swz(p, 16 * it + i)];
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
-    }
-    acc[id / NWV] = c;
-  }
+  dw_tiles_range<TB, TO, TI, false, 0, TI, ACC, NWV>(Xs, Ys, acc, w, lane);
 }
 
 // Write rows (lane order: unit 16b + 4g + r = v[4b + r]) of this lane's point.
-template <int N>
+template <int N, bool BF = false>
 __device__ __forceinline__ void stage_units(float* S, int pt, int g, const float (&v)[N]) {
 #pragma unroll
-  for (int b = 0; b < N / 4; ++b)
-    *reinterpret_cast<float4*>(S + swz(pt, 16 * b + 4 * g)) = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
-}
-
-// Write a first-layer input vector (lane order) at its canonical columns.
-template <class Sh, int S1>
-__device__ __forceinline__ void stage_inputs(float* S, int pt, int g, const float (&x)[S1], bool colour) {
-#pragma unroll
-  for (int s = 0; s < S1; ++s) {
-    const int col = first_layer_col<Sh::L>(s, g, colour);
-    if (col >= 0) S[swz(pt, col)] = x[s];
+  for (int b = 0; b < N / 4; ++b) {
+    float4 q = make_float4(v[4 * b], v[4 * b + 1], v[4 * b + 2], v[4 * b + 3]);
+    if (BF) q = make_float4(bf16r(q.x), bf16r(q.y), bf16r(q.z), bf16r(q.w));
+    *reinterpret_cast<float4*>(S + swz(pt, 16 * b + 4 * g)) = q;
   }
 }
 
-// Full adjoint of one MLP for the wave's 16 points.  dout: 16-row output
-// gradient tile (lane holds rows 4g..4g+3).  Returns dx (lane input order).
-// Contains workgroup barriers: every thread of the workgroup must call it
-// with the same template arguments.  TB0: first dW tile id of this MLP.
-template <class Sh, bool COL, int S1, int ACC, int NWV>
-__device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const float (&x1)[S1],
-                                             const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
-                                             float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
-                                             int w, int lane) {
+// Write the first-layer inputs of lane k-steps [S0, SE) (lane order) at
+// their canonical columns.
+template <class Sh, int S1, int S0, int SE, bool BF = false>
+__device__ __forceinline__ void stage_inputs(float* S, int pt, int g, const float (&x)[S1], bool colour) {
+#pragma unroll
+  for (int s = S0; s < SE; ++s) {
+    const int col = first_layer_col<Sh::L>(s, g, colour);
+    if (col >= 0) S[swz(pt, col)] = BF ? bf16r(x[s]) : x[s];
+  }
+}
+
+// Output and hidden layers of one MLP's adjoint for the wave's 16 points:
+// their dW tiles, and dh = the gradient of the first layer's pre-activation
+// output.  dout: 16-row output gradient tile (lane holds rows 4g..4g+3).
+// Returns the first layer's adjoint operands.  Contains workgroup barriers:
+// every thread of the workgroup must call it with the same template
+// arguments.
+template <class Sh, bool COL, int ACC, int NWV>
+__device__ __forceinline__ const float* mlp_backward_upper(const float* __restrict__ Wb,
+                                                           const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                                           float (&dh)[Sh::S_HID], float* Xs, float* Ys,
+                                                           v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
-  static_assert(S1 == (COL ? Sh::S_COL1 : Sh::S_GEO1), "first-layer width");
-  constexpr bool colour = COL;
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
   constexpr int TB0 = COL ? B::TILES_GEO : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   // ---- output layer: dW_out += dout (x) h_last
-  {
-    float d4[4] = {dout[0], dout[1], dout[2], dout[3]};
-    *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) = make_float4(d4[0], d4[1], d4[2], d4[3]);
-    stage_units<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
-  }
+  *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) = make_float4(dout[0], dout[1], dout[2], dout[3]);
+  stage_units<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
   __syncthreads();
   constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
   dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
-  float dh[Sh::S_HID];
   {
     float din[4] = {dout[0], dout[1], dout[2], dout[3]};
     v4f acc[Sh::NT];
@@ -203,20 +264,49 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
 #pragma unroll
       for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
   }
-  // ---- first layer: dW_1 += dh (x) x, dx = W_1^T dh
+  return W;
+}
+
+// First layer of the adjoint restricted to the lane input k-steps [S0, SE):
+// dW_1 += dh (x) x over the input tiles [IT0, IT1) (whose columns those
+// k-steps hold) and the rows [S0, SE) of dx = W_1^T dh.  Barriers as above.
+template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV>
+__device__ __forceinline__ void mlp_backward_first(const float* __restrict__ W, const float (&x1)[S1],
+                                                   const float (&dh)[Sh::S_HID], float (&dx)[S1], float* Xs,
+                                                   float* Ys, v4f (&accW)[ACC], int w, int lane) {
+  using B = BwdShape<Sh>;
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  const int j = lane & 15, g = lane >> 4;
+  const int pt = w * 16 + j;
   stage_units<Sh::S_HID>(Ys, pt, g, dh);
-  stage_inputs<Sh, S1>(Xs, pt, g, x1, colour);
+  stage_inputs<Sh, S1, S0, SE>(Xs, pt, g, x1, COL);
   __syncthreads();
-  dw_tiles<TB0, Sh::NT, TI1, ACC, NWV>(Xs, Ys, accW, w, lane);
+  dw_tiles_range<TB0, Sh::NT, TI1, COL, IT0, IT1, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
-  {
-    v4f acc[S1 / 4];
-    mfma_layer<S1 / 4, Sh::S_HID>(W, dh, acc, lane);
+  v4f acc[(SE - S0) / 4];
 #pragma unroll
-    for (int b = 0; b < S1 / 4; ++b)
+  for (int b = 0; b < (SE - S0) / 4; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+  mfma_accum<S0 / 4, SE / 4, Sh::S_HID, 0, Sh::S_HID>(W, dh, acc, lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dx[4 * b + r] = acc[b][r];
-  }
+  for (int b = 0; b < (SE - S0) / 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dx[S0 + 4 * b + r] = acc[b][r];
+}
+
+// Full adjoint of one MLP for the wave's 16 points.  Returns dx (lane input
+// order).  TB0 / tile ids as BwdShape.
+template <class Sh, bool COL, int S1, int ACC, int NWV>
+__device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const float (&x1)[S1],
+                                             const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                             float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
+                                             int w, int lane) {
+  using B = BwdShape<Sh>;
+  static_assert(S1 == (COL ? Sh::S_COL1 : Sh::S_GEO1), "first-layer width");
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  float dh[Sh::S_HID];
+  const float* W = mlp_backward_upper<Sh, COL, ACC, NWV>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
+  mlp_backward_first<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -225,8 +315,6 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
 // same lane order packed 8 per k-step; dW runs on the float32 MFMA over
 // staged operands already rounded to bfloat16 (their products are exact in
 // float32, so this equals a bfloat16 product with float32 accumulation).
-__device__ __forceinline__ float bf16r(float x) { return (float)(__bf16)x; }
-
 template <class Sh>
 __device__ void permute_mlp_bwd_bf16(__bf16* dst, const float* __restrict__ W, bool colour, int tid, int stride) {
   const int n_out = colour ? HYRF_COL_OUT : HYRF_GEO_OUT;
@@ -286,33 +374,42 @@ __device__ __forceinline__ void mlp_forward_keep_bf16(const __bf16* __restrict__
   out = o[0];
 }
 
-template <int N>
-__device__ __forceinline__ void stage_units_bf(float* S, int pt, int g, const float (&v)[N]) {
+template <class Sh, int S1, int SPLIT>
+__device__ __forceinline__ void mlp_forward_keep_rest_bf16(const __bf16* __restrict__ Wf, const float (&x1)[S1],
+                                                           v4f (&acc)[Sh::NT], float (&h)[Sh::NH][Sh::S_HID],
+                                                           v4f& out, int lane) {
+  mfma_accum_bf16<0, Sh::NT, S1, SPLIT, S1>(Wf, x1, acc, lane);
+  const __bf16* W = Wf + Sh::NT * S1 * 64;
+  relu_to_inputs<Sh::NT>(acc, h[0]);
+  v4f a2[Sh::NT];
 #pragma unroll
-  for (int b = 0; b < N / 4; ++b)
-    *reinterpret_cast<float4*>(S + swz(pt, 16 * b + 4 * g)) =
-        make_float4(bf16r(v[4 * b]), bf16r(v[4 * b + 1]), bf16r(v[4 * b + 2]), bf16r(v[4 * b + 3]));
+  for (int k = 1; k < Sh::NH; ++k) {
+    mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, h[k - 1], a2, lane);
+    W += Sh::NT * Sh::S_HID * 64;
+    relu_to_inputs<Sh::NT>(a2, h[k]);
+  }
+  v4f o[1];
+  mfma_layer_bf16<1, Sh::S_HID>(W, h[Sh::NH - 1], o, lane);
+  out = o[0];
 }
 
-template <class Sh, bool COL, int S1, int ACC, int NWV>
-__device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb, const float (&x1)[S1],
-                                                  const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
-                                                  float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
-                                                  int w, int lane) {
+template <class Sh, bool COL, int ACC, int NWV>
+__device__ __forceinline__ const __bf16* mlp_backward_upper_bf16(const __bf16* __restrict__ Wb,
+                                                                 const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                                                 float (&dh)[Sh::S_HID], float* Xs, float* Ys,
+                                                                 v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
-  static_assert(S1 == (COL ? Sh::S_COL1_8 : Sh::S_GEO1_8), "first-layer width");
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
   constexpr int TB0 = COL ? B::TILES_GEO : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) =
       make_float4(bf16r(dout[0]), bf16r(dout[1]), bf16r(dout[2]), bf16r(dout[3]));
-  stage_units_bf<Sh::S_HID>(Xs, pt, g, h[Sh::NH - 1]);
+  stage_units<Sh::S_HID, true>(Xs, pt, g, h[Sh::NH - 1]);
   __syncthreads();
   constexpr int TB_OUT = TB0 + Sh::NT * TI1 + (Sh::NH - 1) * Sh::NT * (Sh::HID / 16);
   dw_tiles<TB_OUT, 1, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
-  float dh[Sh::S_HID];
   {
     const float din[8] = {dout[0], dout[1], dout[2], dout[3], 0.f, 0.f, 0.f, 0.f};
     v4f acc[Sh::NT];
@@ -325,8 +422,8 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
   const __bf16* W = Wb + Sh::NT * 8 * 64;
 #pragma unroll
   for (int k = Sh::NH - 1; k >= 1; --k) {
-    stage_units_bf<Sh::S_HID>(Ys, pt, g, dh);
-    stage_units_bf<Sh::S_HID>(Xs, pt, g, h[k - 1]);
+    stage_units<Sh::S_HID, true>(Ys, pt, g, dh);
+    stage_units<Sh::S_HID, true>(Xs, pt, g, h[k - 1]);
     __syncthreads();
     constexpr int TB_H = TB0 + Sh::NT * TI1;
     dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
@@ -339,23 +436,44 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
 #pragma unroll
       for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
   }
-  stage_units_bf<Sh::S_HID>(Ys, pt, g, dh);
-#pragma unroll
-  for (int s = 0; s < S1; ++s) {
-    const int col = first_layer_col<Sh::L>(s, g, COL);
-    if (col >= 0) Xs[swz(pt, col)] = bf16r(x1[s]);
-  }
+  return W;
+}
+
+template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV>
+__device__ __forceinline__ void mlp_backward_first_bf16(const __bf16* __restrict__ W, const float (&x1)[S1],
+                                                        const float (&dh)[Sh::S_HID], float (&dx)[S1], float* Xs,
+                                                        float* Ys, v4f (&accW)[ACC], int w, int lane) {
+  using B = BwdShape<Sh>;
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  const int j = lane & 15, g = lane >> 4;
+  const int pt = w * 16 + j;
+  stage_units<Sh::S_HID, true>(Ys, pt, g, dh);
+  stage_inputs<Sh, S1, S0, SE, true>(Xs, pt, g, x1, COL);
   __syncthreads();
-  dw_tiles<TB0, Sh::NT, TI1, ACC, NWV>(Xs, Ys, accW, w, lane);
+  dw_tiles_range<TB0, Sh::NT, TI1, COL, IT0, IT1, ACC, NWV>(Xs, Ys, accW, w, lane);
   __syncthreads();
-  {
-    v4f acc[S1 / 4];
-    mfma_layer_bf16<S1 / 4, Sh::S_HID>(W, dh, acc, lane);
+  v4f acc[(SE - S0) / 4];
 #pragma unroll
-    for (int b = 0; b < S1 / 4; ++b)
+  for (int b = 0; b < (SE - S0) / 4; ++b) acc[b] = v4f{0.f, 0.f, 0.f, 0.f};
+  mfma_accum_bf16<S0 / 4, SE / 4, Sh::S_HID, 0, Sh::S_HID>(W, dh, acc, lane);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dx[4 * b + r] = acc[b][r];
-  }
+  for (int b = 0; b < (SE - S0) / 4; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dx[S0 + 4 * b + r] = acc[b][r];
+}
+
+template <class Sh, bool COL, int S1, int ACC, int NWV>
+__device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb, const float (&x1)[S1],
+                                                  const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
+                                                  float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
+                                                  int w, int lane) {
+  using B = BwdShape<Sh>;
+  static_assert(S1 == (COL ? Sh::S_COL1_8 : Sh::S_GEO1_8), "first-layer width");
+  constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
+  float dh[Sh::S_HID];
+  const __bf16* W = mlp_backward_upper_bf16<Sh, COL, ACC, NWV>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
+  mlp_backward_first_bf16<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
 }
 
 }  // namespace hyrf

@@ -50,6 +50,18 @@ struct MlpLds {
     if constexpr (BF) mlp_forward_bf16<Sh, S1>(W, x, out, lane);
     else mlp_forward<Sh, S1>(W, x, out, lane);
   }
+  // colour decoder: the view-independent first-layer part (radiance
+  // features, k-steps [0, FPL)) once, then per view the direction part and
+  // the remaining layers
+  static_assert(Sh::FPL % (BF ? 8 : 4) == 0, "feature k-steps must fill whole MFMA k-groups");
+  static __device__ void col_first(const T* W, const float (&x)[SC], v4f (&acc)[Sh::NT], int lane) {
+    if constexpr (BF) mlp_first_part_bf16<Sh, SC, Sh::FPL>(W, x, acc, lane);
+    else mlp_first_part<Sh, SC, Sh::FPL>(W, x, acc, lane);
+  }
+  static __device__ void col_rest(const T* W, const float (&x)[SC], v4f (&acc)[Sh::NT], v4f& out, int lane) {
+    if constexpr (BF) mlp_forward_rest_bf16<Sh, SC, Sh::FPL>(W, x, acc, out, lane);
+    else mlp_forward_rest<Sh, SC, Sh::FPL>(W, x, acc, out, lane);
+  }
 };
 
 template <class Sh, class TT, bool BF>
@@ -130,7 +142,15 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) a.quat[(size_t)r * n + slot] = q[r] * inv;
     }
-    // colour decoder, once per view
+    // colour decoder (Eq. 6): the first layer's product with the radiance
+    // features once, then per view the direction encoding and the rest
+    v4f col1[Sh::NT];
+    {
+      float xf[M::SC];
+#pragma unroll
+      for (int s = 0; s < M::SC; ++s) xf[s] = s < Sh::FPL ? fr[s] : 0.f;
+      M::col_first(w_col, xf, col1, lane);
+    }
     for (int v = 0; v < a.cams.V; ++v) {
       float oc[3];
       cam_center_f32(a.cams.c[v], oc);
@@ -142,9 +162,12 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
       float xc[M::SC];
 #pragma unroll
       for (int s = 0; s < M::SC; ++s)
-        xc[s] = s < Sh::FPL ? fr[s] : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
+        xc[s] = s < Sh::FPL ? 0.f : (s < Sh::FPL + 6 ? pe[s < Sh::FPL + 6 ? (s - Sh::FPL) : 0] : 0.f);
+      v4f acc[Sh::NT];
+#pragma unroll
+      for (int t = 0; t < Sh::NT; ++t) acc[t] = col1[t];
       v4f oc4;
-      M::template run<M::SC>(w_col, xc, oc4, lane);
+      M::col_rest(w_col, xc, acc, oc4, lane);
       if (g == 0 && valid) {
 #pragma unroll
         for (int c = 0; c < 3; ++c)
