@@ -120,6 +120,70 @@ def cpu_baseline(scene, cam):
             "sample_seconds": round(t3 - t0, 2)}
 
 
+def batched_views_timings(steps: int, warmup: int, cfg_name: str = "c3m_8v"):
+    """Train step and render of the batched-view workload (3M Gaussians, 8
+    views of 1280x720 in one launch), float32 fields and the float16-table /
+    bfloat16-decoder variant; stage times of the serial train step from HIP
+    events on the launch streams."""
+    import numpy as np
+    import torch
+
+    import hyrf_inputs as hi
+    import paper_2509_17083_amd as P
+
+    cfg = hi.CONFIGS[cfg_name]
+    scene = hi.make_scene(cfg)
+    cams = hi.make_cameras(cfg)
+    ds = P.DeviceScene.from_host(scene)
+    ds = ds.reordered(ds.spatial_order())
+    ws = P.Workspace()
+    V, H, W = cfg.n_views, cfg.height, cfg.width
+    target = torch.from_numpy(hi.make_target_image((V, 3, H, W), seed=2001)).cuda()
+    z = torch.zeros_like
+    grads = dict(pos=z(ds.pos), scale_e=z(ds.scale_e), rot_e=None if ds.rot_e is None else z(ds.rot_e),
+                 opac_e=z(ds.opac_e), col_e=z(ds.col_e), table_geo=z(ds.table_geo), table_rad=z(ds.table_rad),
+                 mlp_geo=z(ds.mlp_geo), mlp_col=z(ds.mlp_col))
+
+    def train(d, ev=None, overlap=True):
+        st = P.render(d, cams, P.TRAIN, ws=ws, events=ev)
+        loss, dL = P.l1_loss(st.image, target, ws=ws)
+        for t in grads.values():
+            if t is not None:
+                t.zero_()
+        P.render_backward(d, cams, st, dL, grads=grads, ws=ws, events=ev, overlap=overlap)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn(None)
+        torch.cuda.synchronize()
+        ev = {}
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            fn(ev)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) * 1e3 / steps, ev
+
+    keys = (("query", "query0", "query1"), ("project", "query1", "project1"), ("bin_sort", "bin0", "bin1"),
+            ("composite", "bin1", "composite1"), ("bwd_splats", "bwd_stage1", "bwd_stage2"),
+            ("bwd_decoders", "bwd_stage2", "bwd_stage3"), ("bwd_tables", "bwd_stage3", "bwd_stage4"),
+            ("bwd_bg", "bwd_stage4", "bwd_stage5"), ("bwd_dw", "bwd_stage6", "bwd_stage7"))
+
+    def stages(ev):
+        return {k: round(float(np.mean([_ms(a, b) for a, b in zip(ev[k0], ev[k1])])), 4) for k, k0, k1 in keys
+                if k0 in ev and k1 in ev}
+    out = {"workload": f"{cfg.name}: {cfg.n_gauss} Gaussians, {V} views of {W}x{H} in one launch",
+           "steps": steps, "warmup": warmup}
+    for tag, d in (("fp32", ds), ("f16_tables_bf16_decoders", ds.with_precision(P.F16, P.BF16))):
+        ms_train, _ = timed(lambda ev: train(d))
+        _, ev_s = timed(lambda ev: train(d, ev, overlap=False))
+        ms_render, _ = timed(lambda ev: P.render(d, cams, P.RENDER, ws=ws))
+        out[tag] = {"train_step_ms": round(ms_train, 3), "render_ms": round(ms_render, 3),
+                    "render_ms_per_view": round(ms_render / V, 4), "stage_ms_train_serial": stages(ev_s)}
+        print(f"[bench] {cfg.name} {tag}: train step {ms_train:.3f} ms, render {ms_render:.3f} ms "
+              f"({V} views); serial stages {out[tag]['stage_ms_train_serial']}", file=sys.stderr, flush=True)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
@@ -127,6 +191,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--config", default="c1m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched-views", action="store_true",
+                    help="skip the batched-view workload (3M Gaussians, 8 views in one launch) timed after c1m")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (torch) 5 times: the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -287,6 +353,28 @@ def main():
     ds = ds_dec
     print(f"[bench] single field: train step {ms_train_sf:.3f} ms, render {ms_render_sf:.3f} ms/frame",
           file=sys.stderr, flush=True)
+    # the decoupling ablation at the paper's standard-scene sizes (Sec. 4.1,
+    # Sec. 4.4): decoupled fields of 2^18 (radiance) + 2^17 (geometry) rows
+    # per level against one field of 2^18 rows, same Gaussians and camera
+    sf18 = {}
+    if cfg.log2_T_rad != 18:
+        sc18 = hi.make_scene(hi.with_overrides(cfg, log2_T_rad=18))
+        d18 = P.DeviceScene.from_host(sc18)
+        d18 = d18.reordered(d18.spatial_order())
+        g18 = dict(grads, table_geo=torch.zeros_like(d18.table_geo), table_rad=torch.zeros_like(d18.table_rad))
+        grads_keep = grads
+        for tag, d in (("decoupled_2^18_2^17", d18), ("single_2^18", d18.as_single_field())):
+            ds, grads = d, g18
+            ms_t, _, _ = timed(lambda ev: train_step(None), args.steps)
+            ms_r, _, _ = timed(lambda ev: P.render(ds, cams, P.RENDER, ws=ws, events=None), args.steps)
+            sf18[tag] = {"train_step_ms": round(ms_t, 4), "render_ms": round(ms_r, 4)}
+        ds, grads = ds_dec, grads_keep
+        del d18, g18, sc18
+        sf18["single_over_decoupled_train"] = round(sf18["single_2^18"]["train_step_ms"] /
+                                                    sf18["decoupled_2^18_2^17"]["train_step_ms"], 4)
+        sf18["single_over_decoupled_render"] = round(sf18["single_2^18"]["render_ms"] /
+                                                     sf18["decoupled_2^18_2^17"]["render_ms"], 4)
+        print(f"[bench] decoupling ablation at 2^18: {sf18}", file=sys.stderr, flush=True)
 
     # fused Adam over every trained tensor (explicit Gaussians, both tables,
     # both decoders), gradients cleared in the same pass
@@ -495,7 +583,8 @@ def main():
                                     "psnr_vs_fp32_render_db": round(psnr_q, 2)},
            "single_field": {"train_step_ms": round(ms_train_sf, 4), "render_ms": round(ms_render_sf, 4),
                             "render_fps": round(1000.0 / ms_render_sf, 2),
-                            "table": f"radiance table only, 2^{cfg.log2_T_rad} rows per level"},
+                            "table": f"radiance table only, 2^{cfg.log2_T_rad} rows per level",
+                            "ablation_at_2^18": sf18},
            "adam_step": {"ms": round(ms_adam, 4), "parameters": n_params, "bytes_per_parameter": 32,
                          "hbm_frac": round(adam_gbs / HBM_PEAK_GBS, 4)},
            "train_step_l1_dssim_ms": round(ms_train_ds, 4),
@@ -506,6 +595,12 @@ def main():
            "roofline_render": roof_fwd,
            "stage_rooflines": stage_roofs,
            "measured_peaks": measured}
+    if args.config == "c1m" and not args.no_batched_views:
+        # the batched-view workload beside the headline (its own scene and buffers)
+        ds = ds_fp32 = ds_dec = grads = st = st_r = st_q = target = img_t = None
+        ws.bufs.clear()
+        torch.cuda.empty_cache()
+        out["batched_views"] = batched_views_timings(min(args.steps, 10), min(args.warmup, 2))
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on a bounded sample ...", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(scene, cams[0])

@@ -60,6 +60,8 @@ def test_single_field_indices_and_features():
 @pytest.mark.parametrize("cfg_name,over", [
     ("tiny", {}),
     ("c100k", {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 16}),
+    # the single field of the decoupling ablation: 2^18 rows per level (Sec. 4.4)
+    ("c100k", {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 18}),
 ])
 def test_single_field_render_matches_oracle(mode, cfg_name, over):
     import paper_2509_17083_amd as P
@@ -76,9 +78,13 @@ def test_single_field_render_matches_oracle(mode, cfg_name, over):
     assert res["ok"], res
 
 
-def test_single_field_backward_matches_oracle():
+@pytest.mark.parametrize("cfg_name,over", [
+    ("tiny", {}),
+    ("c100k", {"n_gauss": 3000, "width": 96, "height": 72, "focal": 110.0, "log2_T_rad": 18}),
+])
+def test_single_field_backward_matches_oracle(cfg_name, over):
     import paper_2509_17083_amd as P
-    cfg, scene, cams = make("tiny", table_init=1.0)
+    cfg, scene, cams = make(cfg_name, table_init=1.0, **over)
     scene.scale_e += np.float32(1.0)
     cam = cams[0]
     H, W = cam.height, cam.width

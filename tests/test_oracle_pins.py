@@ -651,3 +651,20 @@ def test_comparison_rule_explains_one_flipped_decision_only():
     res = parity.compare_pixels(bad, r)
     assert res["n_bad"] == 1 and not res["ok"]
     assert parity.compare_pixels(img, r)["ok"]
+
+
+def test_oracle_gradient_matches_central_differences_at_the_100k_workload():
+    """SURVEY-style pin of the oracle's gradient at scale: the 100k-Gaussian
+    800x800 workload (L = 16, T = 2^19, 2x64 decoders), L = sum(w * C) over
+    64 seeded pixels, 6 seeded directions on a 1% subset of every parameter
+    tensor: central differences of the FP64 forward equal the autograd
+    gradient's projection to 1e-6 (shrinking the step past grid-cell kinks)."""
+    import sys, os
+    sys.path.insert(0, os.path.dirname(__file__))
+    from _hyrf_testutil import DirectionalCase
+    case = DirectionalCase("c100k", n_pixels=64, seed=43)
+    used = 0
+    for it in range(6):
+        fd, an, scale, ok = case.check_fd(case.direction(2000 + it))
+        used += ok
+    assert used >= 6, used
