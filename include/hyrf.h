@@ -110,8 +110,8 @@ typedef struct {
   /* Adjoint only; no effect on any result beyond float rounding.  How the
    * background points' radiance-table scatter treats corners shared by
    * consecutive grid cells: 0 = automatic (merged into one cell before the
-   * atomics with bfloat16 decoders, where the atomic requests bound the
-   * scatter; not with float32 decoders), 1 = always merged, 2 = never.
+   * atomics: fewer atomic requests, for both decoder precisions),
+   * 1 = always merged, 2 = never.
    * Other values: HYRF_ERR_INVALID_ARGUMENT. */
   int32_t scatter_merge;
 } hyrf_fields;

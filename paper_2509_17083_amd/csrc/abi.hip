@@ -533,7 +533,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.feat_geo = q->feat_geo;
   F.feat_rad = q->feat_rad;
   F.jac = q->feat_jac;
-  F.merge = fields->scatter_merge == 1 ? 1 : fields->scatter_merge == 2 ? 0 : (fields->mlp_dtype == HYRF_BF16 ? 1 : 0);
+  F.merge = fields->scatter_merge == 2 ? 0 : 1;
   F.dgeo = w.dgeo;
   F.dcol = w.dcol;
   F.dfeat_geo = w.dfeat_geo;

