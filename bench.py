@@ -112,12 +112,50 @@ def cpu_baseline(scene, cam):
     scale_px = stride * (tiles_x * tiles_y) / len(pick)
     full_ms = ((fg + bg_) * stride + (fp + bp) * scale_px) * 1e3
     fwd_ms = (fg * stride + fp * scale_px) * 1e3
+    # the oracle's whole step, measured end to end where it fits in seconds:
+    # the 1,000-Gaussian 64x64 workload, on every host thread and on one
+    from oracle.time_full_step import time_step
+    full_tiny = [time_step("tiny", n, repeats=3) for n in (torch.get_num_threads(), 1)]
     return {"value": round(1000.0 / full_ms, 7), "unit": "train steps/s (fwd+L1+bwd)", "ms_per_step": round(full_ms, 1),
+            "value_is": "an estimate: the sample's times scaled to the full 1M-Gaussian 1080p step; "
+                        "measured_full_steps are whole oracle steps timed end to end",
+            "measured_full_steps": [{k: f[k] for k in ("config", "gaussians", "image", "threads",
+                                                        "train_step_ms_median")} for f in full_tiny],
             "render_ms_per_frame": round(fwd_ms, 1), "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"FP64 oracle: one Gaussian in {stride} ({len(sel)}) through query+projection, "
                       f"{len(pick)} random 16x16 tiles through blending + background + L1, autograd backward; "
                       f"scaled x{stride} per Gaussian and x{stride}x{tiles_x * tiles_y}/{len(pick)} per pixel",
             "sample_seconds": round(t3 - t0, 2)}
+
+
+def gather_reference():
+    """Committed rocprofv3 record of the random-gather reference kernel
+    (its 128-byte read requests per launch), or None."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "traffic_c1m_fp32.json")) as f:
+            return json.load(f).get("random_gather_reference")
+    except (OSError, ValueError):
+        return None
+
+
+def random_gather_ms(launches: int = 5):
+    """Average time of torch's gather of 64M random 8-byte entries from a
+    256 MiB table (about the size of the float32 radiance table): every read
+    a separate cache line, the reference for the hash-grid gathers."""
+    import torch
+    table = torch.arange(32 << 20, dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, table.numel(), (64 << 20,), device="cuda", generator=torch.Generator("cuda").manual_seed(9))
+    out = torch.empty(idx.numel(), dtype=torch.int64, device="cuda")
+    torch.index_select(table, 0, idx, out=out)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(launches):
+        torch.index_select(table, 0, idx, out=out)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / launches
+    del table, idx, out
+    return ms
 
 
 def batched_views_timings(steps: int, warmup: int, cfg_name: str = "c3m_8v"):
@@ -196,6 +234,9 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 256 MiB device copy (torch) 5 times: the reference kernel for "
                          "scaling rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--calibrate-gather", action="store_true",
+                    help="only run torch's gather of 64M random 8-byte entries from a 256 MiB table 5 times: the "
+                         "reference kernel for the memory system's random-read request rate")
     ap.add_argument("--render-only", action="store_true", help="time only the render-mode forward")
     ap.add_argument("--fp32-only", action="store_true",
                     help="time only the float32 train step and render (no variants; for profiler runs)")
@@ -220,6 +261,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "device copy", "bytes_read": src.numel() * 4,
                           "bytes_written": dst.numel() * 4, "launches": 5}))
+        return
+
+    if args.calibrate_gather:
+        torch.cuda.set_device(0)
+        ms = random_gather_ms()
+        print(json.dumps({"calibration": "random gather", "gathers": 64 << 20, "entry_bytes": 8,
+                          "table_bytes": 256 << 20, "ms_per_launch": round(ms, 4),
+                          "G_gathers_per_s": round((64 << 20) / (ms * 1e-3) / 1e9, 2)}))
         return
 
     import hyrf_inputs as hi
@@ -472,7 +521,27 @@ def main():
     roof_fwd = {"kernel": "k_field_query", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": measured_traffic("k_field_query"), "algorithmic_bytes": n_vis * per_g,
-                "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4)}
+                "bytes_per_gaussian": per_g, "gaussians": n_vis, "kernel_ms": round(q_ms, 4),
+                "timed": "hyrf_query_fields (pre-cull, its scan and the field query) on the launch stream"}
+    if roof_fwd["traffic"]:
+        # what the memory system really moved: whole lines per hashed corner
+        tr_gbs = roof_fwd["traffic"] / (q_ms * 1e-3) / 1e9
+        roof_fwd.update({"traffic_GBs": round(tr_gbs, 1), "traffic_frac": round(tr_gbs / HBM_PEAK_GBS, 4),
+                         "traffic_over_algorithmic": round(roof_fwd["traffic"] / (n_vis * per_g), 2)})
+    # the gather's real bound: 128-byte line requests past the L2.  Reference
+    # rate: torch's gather of 64M random 8-byte entries of a 256 MiB table,
+    # timed here, with its requests per launch from the committed counters
+    rq = measured_traffic("k_field_query", "l2_read_requests_128B")
+    ref = gather_reference()
+    if rq and ref:
+        ref_rate = ref["l2_read_requests_128B"] / (random_gather_ms() * 1e-3)
+        roof_fwd["line_requests"] = {
+            "l2_read_requests_128B_per_launch": rq, "per_gaussian": round(rq / n_vis, 1),
+            "requests_per_s": round(rq / (q_ms * 1e-3) / 1e9, 1),
+            "random_gather_requests_per_s_measured": round(ref_rate / 1e9, 1), "unit": "G/s",
+            "frac_of_measured_random_line_rate": round(rq / (q_ms * 1e-3) / ref_rate, 3),
+            "reference": "torch index_select of 64M random 8-byte entries of a 256 MiB table "
+                         "(rocprofv3 TCC_EA0_RDREQ_sum per launch, committed)"}
 
     # Measured denominators beside the vendor peaks: a plain device copy
     # (HBM), a library FP32 / BF16 GEMM (MFMA) and the random float-atomic
@@ -500,11 +569,13 @@ def main():
         g1.record()
         torch.cuda.synchronize()
         return 5 * 2 * 8192 ** 3 / (g0.elapsed_time(g1) * 1e-3) / 1e12
+    gather_rate = (64 << 20) / (random_gather_ms() * 1e-3)
     measured = {"hbm_copy_GBs": round(copy_gbs, 1), "fp32_gemm_TFLOPs": round(gemm_tflops(torch.float32), 1),
+                "random_8B_gathers_G_per_s": round(gather_rate / 1e9, 2),
                 "bf16_gemm_TFLOPs": round(gemm_tflops(torch.bfloat16), 1),
                 "random_float_atomics_G_per_s": round(atomic_rate / 1e9, 1),
                 "how": "torch copy_ of 1 GiB (read + write); torch.mm 8192^3; torch index_add_ of 64M values "
-                       "at random indices"}
+                       "at random indices; torch index_select of 64M random 8-byte entries of a 256 MiB table"}
 
     # Every stage against its own bound (FP32 fields, serial stage times),
     # with the algorithmic work per unit of the method: bytes for the
