@@ -455,6 +455,10 @@ def main():
     psnr_q = float(-10.0 * torch.log10(torch.mean((q_img - ref_img) ** 2)))
     dqb = dataclasses.replace(dq, mlp_dtype=P.BF16)
     ms_render_qb, _, _ = timed(lambda ev: P.render(dqb, cams, P.RENDER, ws=ws, events=None), args.steps)
+    # the whole compressed model: float16 positions as well
+    dqh = dq.with_half_positions()
+    ms_render_qh, _, _ = timed(lambda ev: P.render(dqh, cams, P.RENDER, ws=ws, events=None), args.steps)
+    del dqh
     print(f"[bench] render (u8 tables) {ms_render_q:.3f} ms/frame; stages {st_render_q}; PSNR vs FP32 render "
           f"{psnr_q:.2f} dB; with bf16 decoders {ms_render_qb:.3f} ms", file=sys.stderr, flush=True)
     del dq, dqb
@@ -651,6 +655,7 @@ def main():
            "compressed_u8_tables": {"render_ms": round(ms_render_q, 4), "render_fps": round(1000.0 / ms_render_q, 2),
                                     "stage_ms_render": {k: round(v, 4) for k, v in st_render_q.items()},
                                     "render_ms_bf16_decoders": round(ms_render_qb, 4),
+                                    "render_ms_with_f16_positions": round(ms_render_qh, 4),
                                     "psnr_vs_fp32_render_db": round(psnr_q, 2)},
            "single_field": {"train_step_ms": round(ms_train_sf, 4), "render_ms": round(ms_render_sf, 4),
                             "render_fps": round(1000.0 / ms_render_sf, 2),

@@ -65,11 +65,18 @@ typedef enum { HYRF_RENDER = 0, HYRF_TRAIN = 1 } hyrf_mode;
 /* Explicit compact Gaussians (Sec. 3.2, first paragraph). */
 typedef struct {
   int32_t n;
-  const float* pos;      /* [3][n] world position p_e                              */
+  const void* pos;       /* [3][n] world position p_e: float32, or float16 when
+                            pos_dtype = HYRF_F16 (see below)                       */
   const float* scale_e;  /* [3][n] scale logit s_e (paper: one value; pass equal axes) */
   const float* rot_e;    /* [4][n] rotation residual (w,x,y,z) or NULL (paper: none) */
   const float* opac_e;   /* [n]    opacity logit alpha_e                           */
   const float* col_e;    /* [3][n] colour logit c_e                                */
+  /* HYRF_F32 (0, the default) or HYRF_F16: positions stored in half
+   * precision, the compressed model's format (Sec. 4.3), widened to float32
+   * (exactly) where the cull, the field query and the projection read them.
+   * A render-only format: hyrf_render_backward and its stages reject it
+   * (HYRF_ERR_UNSUPPORTED); hyrf_spatial_order takes float32 positions. */
+  int32_t pos_dtype;
 } hyrf_gaussians;
 
 /* Two hash-grid fields and their decoders (Sec. 3.2, Eqs. 2-6; Sec. 4.1). */

@@ -22,7 +22,8 @@ P = C.c_void_p
 
 
 class hyrf_gaussians(C.Structure):
-    _fields_ = [("n", C.c_int32), ("pos", P), ("scale_e", P), ("rot_e", P), ("opac_e", P), ("col_e", P)]
+    _fields_ = [("n", C.c_int32), ("pos", P), ("scale_e", P), ("rot_e", P), ("opac_e", P), ("col_e", P),
+                ("pos_dtype", C.c_int32)]
 
 
 class hyrf_fields(C.Structure):

@@ -80,6 +80,8 @@ hyrf_status check_gauss(const hyrf_gaussians* g) {
   REQ(g, "gaussians is NULL");
   REQ(g->n >= 0, "gaussian count must be >= 0");
   if (g->n > 0) REQ(g->pos && g->scale_e && g->opac_e && g->col_e, "a gaussian array is NULL");
+  REQ(g->pos_dtype == HYRF_F32 || g->pos_dtype == HYRF_F16, "pos_dtype = %d must be HYRF_F32 or HYRF_F16",
+      g->pos_dtype);
   return HYRF_OK;
 }
 
@@ -174,7 +176,7 @@ void launch_query_all(const hyrf_fields* fields, const hyrf_gaussians* g, const 
   uint32_t *flag, *pos, *temp;
   query_ws(g->n, &flag, &pos, &temp, ws);
   const Cams cc = make_cams(cams, n_views);
-  launch_cull(g->pos, g->n, cc, flag, pos, temp, out->vis_idx, out->vis_count, st);
+  launch_cull(g->pos, g->pos_dtype == HYRF_F16, g->n, cc, flag, pos, temp, out->vis_idx, out->vis_count, st);
   if (g->n > 0) {
     QueryArgs a{};
     a.grid = make_grid(fields);
@@ -187,6 +189,7 @@ void launch_query_all(const hyrf_fields* fields, const hyrf_gaussians* g, const 
     a.count = out->vis_count;
     a.vis_idx = out->vis_idx;
     a.pos = g->pos;
+    a.pos_f16 = g->pos_dtype == HYRF_F16;
     a.scale_e = g->scale_e;
     a.rot_e = g->rot_e;
     a.opac_e = g->opac_e;
@@ -242,6 +245,7 @@ hyrf_status hyrf_project(const hyrf_gaussians* g, const hyrf_query_out* q, const
   a.count = q->vis_count;
   a.vis_idx = q->vis_idx;
   a.pos = g->pos;
+  a.pos_f16 = g->pos_dtype == HYRF_F16;
   a.opacity = q->opacity;
   a.scale = q->scale;
   a.quat = q->quat;
@@ -462,6 +466,8 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   if (fields->table_dtype == HYRF_U8)
     return fail(HYRF_ERR_UNSUPPORTED, "8-bit quantised tables are a render-only format (no backward)");
   if ((s = check_gauss(g)) != HYRF_OK) return s;
+  if (g->pos_dtype != HYRF_F32)
+    return fail(HYRF_ERR_UNSUPPORTED, "float16 positions are a render-only format (no backward)");
   if ((s = check_cams(cams, n_views)) != HYRF_OK) return s;
   REQ(saved && saved->query && saved->splats, "saved forward state is incomplete");
   const hyrf_query_out* q = saved->query;
@@ -505,7 +511,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   L.proj.n_max = sp->n_max;
   L.proj.count = q->vis_count;
   L.proj.vis_idx = q->vis_idx;
-  L.proj.pos = g->pos;
+  L.proj.pos = static_cast<const float*>(g->pos);
   L.proj.opacity = q->opacity;
   L.proj.scale = q->scale;
   L.proj.quat = q->quat;
@@ -528,7 +534,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.n = g->n;
   F.count = q->vis_count;
   F.vis_idx = q->vis_idx;
-  F.pos = g->pos;
+  F.pos = static_cast<const float*>(g->pos);
   F.rot_e = g->rot_e;
   F.feat_geo = q->feat_geo;
   F.feat_rad = q->feat_rad;

@@ -16,6 +16,12 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 namespace hyrf {
 
+// Coordinate i of a planar position array stored as float32 or, for the
+// compressed model, float16 (widened exactly).
+__device__ __forceinline__ float load_pos(const void* pos, bool f16, size_t i) {
+  return f16 ? (float)reinterpret_cast<const _Float16*>(pos)[i] : reinterpret_cast<const float*>(pos)[i];
+}
+
 constexpr int TILE = HYRF_TILE;
 constexpr int MAXV = HYRF_MAX_VIEWS;
 constexpr float ALPHA_MIN = 1.0f / 255.0f;   // 3DGS: skip splats below this alpha

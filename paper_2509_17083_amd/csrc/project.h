@@ -10,7 +10,8 @@ struct ProjArgs {
   int tiles_x, tiles_y;
   const int32_t* count;
   const int32_t* vis_idx;
-  const float* pos;
+  const void* pos;
+  bool pos_f16;
   const float* opacity;
   const float* scale;
   const float* quat;

@@ -17,7 +17,8 @@ __global__ __launch_bounds__(256) void k_project(ProjArgs a) {
   if (s < count) {
     const int n = a.n;
     const int gi = a.vis_idx[s];
-    const float pxf = a.pos[gi], pyf = a.pos[n + gi], pzf = a.pos[2 * n + gi];
+    const float pxf = load_pos(a.pos, a.pos_f16, gi), pyf = load_pos(a.pos, a.pos_f16, (size_t)n + gi),
+                pzf = load_pos(a.pos, a.pos_f16, 2 * (size_t)n + gi);
     double t[3];
     cam_space_f64(c, (double)pxf, (double)pyf, (double)pzf, t);
     const bool vis = precull_f64(c, t);

@@ -17,7 +17,8 @@ struct QueryArgs {
   int n;                      // Gaussian count (stride of the planar arrays)
   const int32_t* count;       // survivors
   const int32_t* vis_idx;
-  const float* pos;
+  const void* pos;
+  bool pos_f16;
   const float* scale_e;
   const float* rot_e;
   const float* opac_e;
@@ -53,7 +54,7 @@ void launch_query(int L, int hid, int nh, int tdt, bool bf, const QueryArgs& a, 
 void launch_bg(int L, int hid, int nh, int tdt, bool bf, const BgArgs& a, int n_cap, hipStream_t st);
 // rgb[v][c][p] += T[v][p] * bg[v][c][p]
 void launch_blend_bg(const float* bg, const float* T, float* rgb, int V, int HW, hipStream_t st);
-void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
+void launch_cull(const void* pos, bool pos_f16, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
                  uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st);
 
 }  // namespace hyrf

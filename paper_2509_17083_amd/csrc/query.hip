@@ -10,11 +10,12 @@
 namespace hyrf {
 
 // ---------------------------------------------------------------- pre-cull
-__global__ __launch_bounds__(256) void k_cull_flags(const float* __restrict__ pos, int n, Cams cams,
+__global__ __launch_bounds__(256) void k_cull_flags(const void* __restrict__ pos, bool pos_f16, int n, Cams cams,
                                                     uint32_t* __restrict__ flag) {
   const int i = blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const double px = pos[i], py = pos[n + i], pz = pos[2 * n + i];
+  const double px = load_pos(pos, pos_f16, i), py = load_pos(pos, pos_f16, (size_t)n + i),
+               pz = load_pos(pos, pos_f16, 2 * (size_t)n + i);
   bool keep = false;
   for (int v = 0; v < cams.V; ++v) {
     double t[3];
@@ -87,7 +88,8 @@ __global__ __launch_bounds__(QUERY_NT, 2) void k_field_query(QueryArgs a) {
     const int slot = grp * 16 + j;
     const bool valid = slot < count;
     const int gi = valid ? a.vis_idx[slot] : a.vis_idx[0];
-    const float pxf = a.pos[gi], pyf = a.pos[n + gi], pzf = a.pos[2 * n + gi];
+    const float pxf = load_pos(a.pos, a.pos_f16, gi), pyf = load_pos(a.pos, a.pos_f16, (size_t)n + gi),
+                pzf = load_pos(a.pos, a.pos_f16, 2 * (size_t)n + gi);
     double x[3];
     contract_f64(a.grid, (double)pxf, (double)pyf, (double)pzf, x);
     float fg[Sh::FPL], fr[Sh::FPL];
@@ -316,14 +318,14 @@ void launch_blend_bg(const float* bg, const float* T, float* rgb, int V, int HW,
   k_blend_bg<<<(unsigned)((n + 255) / 256), 256, 0, st>>>(bg, T, rgb, HW, n);
 }
 
-void launch_cull(const float* pos, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
+void launch_cull(const void* pos, bool pos_f16, int n, const Cams& cams, uint32_t* flag, uint32_t* pos_,
                  uint32_t* scan_temp, int32_t* vis_idx, int32_t* vis_count, hipStream_t st) {
   if (n <= 0) {
     scan_exclusive_u32(nullptr, nullptr, 0, scan_temp, (uint32_t*)vis_count, st);
     return;
   }
   const int nb = (n + 255) / 256;
-  k_cull_flags<<<nb, 256, 0, st>>>(pos, n, cams, flag);
+  k_cull_flags<<<nb, 256, 0, st>>>(pos, pos_f16, n, cams, flag);
   scan_exclusive_u32(flag, pos_, n, scan_temp, (uint32_t*)vis_count, st);
   k_cull_write<<<nb, 256, 0, st>>>(flag, pos_, n, vis_idx);
 }

@@ -52,6 +52,7 @@ class DeviceScene:
     mlp_dtype: int = F32
     qparams_geo: Optional[torch.Tensor] = None   # (L, 2) (min, step) for U8 tables
     qparams_rad: Optional[torch.Tensor] = None
+    pos_dtype: int = F32     # F16: positions stored in half precision (render-only)
     single_field: int = 0    # one field (the radiance table) feeds both decoders
     scatter_merge: int = 0   # background table scatter: 0 automatic, 1 merge shared corners, 2 never
 
@@ -108,6 +109,14 @@ class DeviceScene:
         return dataclasses.replace(self, table_geo=cg, table_rad=cr, table_dtype=U8, qparams_geo=qg, qparams_rad=qr,
                                    mlp_dtype=self.mlp_dtype if mlp_dtype is None else mlp_dtype)
 
+    def with_half_positions(self) -> "DeviceScene":
+        """The same scene with its positions stored in float16 (rounded to
+        nearest even): the compressed model's position format, a
+        render-only format decoded where the kernels read positions."""
+        import dataclasses
+        assert self.pos_dtype == F32
+        return dataclasses.replace(self, pos=self.pos.to(torch.float16).contiguous(), pos_dtype=F16)
+
     def as_single_field(self) -> "DeviceScene":
         """The single-field (non-decoupled) model: the radiance table alone
         feeds both decoders."""
@@ -117,6 +126,7 @@ class DeviceScene:
 
     def spatial_order(self) -> torch.Tensor:
         """Morton-order permutation of the Gaussians (computed on the GPU)."""
+        assert self.pos_dtype == F32, "spatial_order takes float32 positions"
         lib = A.load()
         n = self.n
         perm = torch.empty(max(n, 1), dtype=torch.int32, device=self.pos.device)
@@ -159,6 +169,7 @@ class DeviceScene:
         g.pos, g.scale_e, g.opac_e, g.col_e = (self.pos.data_ptr(), self.scale_e.data_ptr(),
                                                self.opac_e.data_ptr(), self.col_e.data_ptr())
         g.rot_e = None if self.rot_e is None else self.rot_e.data_ptr()
+        g.pos_dtype = int(self.pos_dtype)
         return g
 
 

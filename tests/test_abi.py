@@ -152,3 +152,16 @@ def test_background_entry_points_reject_bad_arguments():
         A.HYRF_ERR_INVALID_ARGUMENT
     assert lib.hyrf_blend_background(C.c_void_p(0x1), C.c_void_p(0x100), C.c_void_p(0x200), 1, 0, 4, None) == \
         A.HYRF_ERR_INVALID_ARGUMENT
+
+
+def test_query_rejects_bad_position_dtype():
+    A, lib = _lib()
+    f = _fields(A)
+    g = A.hyrf_gaussians()
+    g.n = 10
+    g.pos = g.scale_e = g.opac_e = g.col_e = 0x2000
+    g.pos_dtype = 7
+    o = A.hyrf_query_out()
+    o.vis_count = o.vis_idx = o.opacity = o.scale = o.quat = o.rgb = 0x3000
+    st = lib.hyrf_query_fields(C.byref(f), C.byref(g), _cam(A), 1, C.byref(o), C.c_void_p(0x4000), 1 << 20, None)
+    assert st == A.HYRF_ERR_INVALID_ARGUMENT and b"pos_dtype" in lib.hyrf_last_error()

@@ -128,3 +128,58 @@ def test_quantized_tables_have_no_backward():
     with pytest.raises(A.HyrfError) as e:
         P.render_backward(ds, cams, st, dL)
     assert e.value.status == A.HYRF_ERR_UNSUPPORTED
+
+
+def _half_positions(scene):
+    """The scene with its positions rounded to float16 (nearest even) and
+    widened back: what a render from float16 positions sees."""
+    sr = copy.deepcopy(scene)
+    sr.pos = scene.pos.astype(np.float16).astype(np.float32)
+    return sr
+
+
+MID = {"n_gauss": 20000, "width": 250, "height": 190, "focal": 300.0, "log2_T_rad": 16}
+
+
+@pytest.mark.parametrize("mode", [O.TRAIN, O.RENDER])
+def test_half_positions_render(mode):
+    """Positions stored in float16 (Sec. 4.3, compressed model), widened
+    where the cull, the query and the projection read them: the render
+    equals, bit for bit, the float32 render of the rounded positions, and
+    matches the FP64 oracle of the rounded scene; with 8-bit tables as well
+    (the whole compressed model) it matches the oracle fed both."""
+    import paper_2509_17083_amd as P
+    cfg, scene, cams = make("c100k", table_init=1.0, **MID)
+    scene.scale_e += np.float32(1.0)
+    H, W = cams[0].height, cams[0].width
+    ds = P.DeviceScene.from_host(scene)
+    d16 = ds.with_half_positions()
+    sr = _half_positions(scene)
+    dr = P.DeviceScene.from_host(sr)
+    a = P.render(d16, cams, mode)
+    b = P.render(dr, cams, mode)
+    torch.cuda.synchronize()
+    assert int(a.query["vis_count"].item()) == int(b.query["vis_count"].item())
+    assert torch.equal(a.image, b.image) and torch.equal(a.T, b.T)
+    res = compare_image(a.image[0].cpu().numpy(), oracle_view(sr, cams[0], mode), mode, H, W)
+    _say("half positions", res)
+    assert res["ok"], res
+    # the whole compressed model: float16 positions and 8-bit tables
+    dq = ds.quantized().with_half_positions()
+    c = P.render(dq, cams, mode)
+    torch.cuda.synchronize()
+    r, _, _ = _oracle_quant(sr, cams[0], mode)
+    res = compare_image(c.image[0].cpu().numpy(), r, mode, H, W)
+    _say("half positions + 8-bit tables", res)
+    assert res["ok"], res
+
+
+def test_half_positions_have_no_backward():
+    import paper_2509_17083_amd as P
+    from paper_2509_17083_amd import _abi as A
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    ds = P.DeviceScene.from_host(scene).with_half_positions()
+    st = P.render(ds, cams, P.TRAIN)
+    with pytest.raises(A.HyrfError) as e:
+        P.render_backward(ds, cams, st, torch.ones_like(st.image))
+    assert e.value.status == A.HYRF_ERR_UNSUPPORTED
