@@ -333,3 +333,38 @@ def _permuted(scene, p):
     sc2.rot_e = None if scene.rot_e is None else scene.rot_e[:, p].copy()
     sc2.opac_e, sc2.col_e = scene.opac_e[p].copy(), scene.col_e[:, p].copy()
     return sc2
+
+
+def test_render_with_no_gaussians_is_the_background_and_its_gradient():
+    """n = 0 (empty explicit arrays): the image is the neural background in
+    both modes, and the adjoint reaches only the radiance table and the
+    colour decoder, as in the oracle."""
+    import copy
+    P = _P()
+    cfg, scene, cams = make("tiny", table_init=1.0)
+    s0 = copy.deepcopy(scene)
+    s0.pos, s0.scale_e, s0.rot_e = scene.pos[:, :0].copy(), scene.scale_e[:, :0].copy(), scene.rot_e[:, :0].copy()
+    s0.opac_e, s0.col_e = scene.opac_e[:0].copy(), scene.col_e[:, :0].copy()
+    ds = device_scene(s0)
+    assert ds.n == 0
+    for mode in (O.TRAIN, O.RENDER):
+        st = P.render(ds, cams, mode)
+        torch.cuda.synchronize()
+        assert int(st.query["vis_count"].item()) == 0 and st.n_entries == 0
+        r = oracle_view(s0, cams[0], mode)
+        res = compare_image(st.image[0].cpu().numpy(), r, mode, 64, 64)
+        assert res["ok"], res
+    w = torch.from_numpy(hi.make_target_image((1, 3, 64, 64), seed=12) - 0.5)
+    st = P.render(ds, cams, P.TRAIN)
+    g = P.render_backward(ds, cams, st, w.float().cuda())
+    torch.cuda.synchronize()
+    params, fields = O.from_scene(s0, requires_grad=True)
+    r = O.render_view(params, fields, cams[0], O.TRAIN)
+    L = torch.sum(r["rgb"].T.reshape(3, 64, 64) * w[0].double())
+    gt, *gm = torch.autograd.grad(L, [fields.table_rad] + list(fields.mlp_col))
+    e_t = float((g["table_rad"].cpu().double() - gt).norm() / gt.norm())
+    e_m = float((g["mlp_col"].cpu().double() - torch.cat([x.reshape(-1) for x in gm])).norm() /
+                torch.cat([x.reshape(-1) for x in gm]).norm())
+    print("no Gaussians: gradient relative L2 table_rad %.2e mlp_col %.2e" % (e_t, e_m), flush=True)
+    assert e_t < 1e-3 and e_m < 1e-3
+    assert float(g["table_geo"].abs().max()) == 0.0 and float(g["mlp_geo"].abs().max()) == 0.0
