@@ -672,7 +672,10 @@ __device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, const fl
 template <bool RAY>
 constexpr int bwd_waves() { return RAY ? 8 : 4; }
 
-template <class Sh, bool RAY, class TT, bool BF>
+// SAVED (background points): the forward kept their radiance features
+// (a.bg_feat), and the kernel carries no gather (60 fewer registers per
+// lane); else the adjoint gathers them again.
+template <class Sh, bool RAY, class TT, bool BF, bool SAVED = false>
 __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArgs a) {
   using B = BwdShape<Sh>;
   using D = Dec<Sh, BF>;
@@ -803,7 +806,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         sx[3 * pl + 1] = x[1];
         sx[3 * pl + 2] = x[2];
       }
-      if (a.bg_feat) {
+      if constexpr (SAVED) {
         // features saved by the forward
 #pragma unroll
         for (int k = 0; k < Sh::L / 4; ++k) {
@@ -1157,7 +1160,10 @@ static void launch_bwd_t(const BwdLaunch& L, hipStream_t st) {
   if ((L.stages & BWD_STAGE_BG_DECODERS) && L.with_bg) {
     FieldBwdArgs b = a;
     b.dw_part = a.dw_part + (size_t)L.blocks_g * a.n_w;
-    k_field_bwd<Sh, true, TT, BF><<<L.blocks_r, bwd_waves<true>() * 64, 0, st>>>(b);
+    if (b.bg_feat)
+      k_field_bwd<Sh, true, TT, BF, true><<<L.blocks_r, bwd_waves<true>() * 64, 0, st>>>(b);
+    else
+      k_field_bwd<Sh, true, TT, BF, false><<<L.blocks_r, bwd_waves<true>() * 64, 0, st>>>(b);
   }
   if (L.stages & BWD_STAGE_DW) {
     const int parts = L.blocks_g + (L.with_bg ? L.blocks_r : 0);
