@@ -156,6 +156,34 @@ def test_background_scatter_corner_merging_changes_only_rounding():
         assert float(g_off["table_rad"].abs().max()) > 0
 
 
+def test_background_adjoint_saved_and_gathered_features_agree():
+    """The background adjoint has two instances: one reads the radiance
+    features the forward kept, the other gathers them again from the table
+    (when the forward kept none).  On a scene whose background covers most
+    pixels, with float32 and float16 tables and float32 and bfloat16
+    decoders, both give the same gradients up to the order of the float
+    atomics."""
+    import dataclasses
+    P = _P()
+    cfg, scene, cams = make("c100k", table_init=1.0, n_gauss=2000, width=200, height=150, focal=180.0,
+                            log2_T_rad=16)
+    ds = device_scene(scene)
+    dL = torch.from_numpy(hi.make_target_image((1, 3, 150, 200), seed=23) - 0.5).cuda()
+    for tdt, dec in ((P.F32, P.F32), (P.F16, P.F32), (P.F32, P.BF16), (P.F16, P.BF16)):
+        d0 = ds.with_precision(tdt, dec)
+        st = P.render(d0, cams, P.TRAIN)
+        assert st.bg_feat is not None
+        g_saved = P.render_backward(d0, cams, st, dL, overlap=False)
+        g_gather = P.render_backward(d0, cams, dataclasses.replace(st, bg_feat=None), dL, overlap=False)
+        torch.cuda.synchronize()
+        for k in ("table_rad", "mlp_col"):
+            a, b = g_gather[k], g_saved[k]
+            rel = float((a - b).norm() / b.norm())
+            print("tables", tdt, "decoders", dec, k, "gathered vs saved relative L2", rel, flush=True)
+            assert rel < 1e-5, (tdt, dec, k, rel)
+        assert float(g_saved["table_rad"].abs().max()) > 0
+
+
 def test_staged_backward_equals_one_call():
     P = _P()
     cfg, scene, cams = make("tiny", table_init=1.0)
