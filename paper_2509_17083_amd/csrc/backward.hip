@@ -491,11 +491,14 @@ __device__ __forceinline__ uint64_t cell_heads(const int (&ci)[3]) {
 }
 
 // Segmented inclusive sums of v over the runs that start at the set bits of
-// `heads`: the last lane of every run ends with the run's totals.  Only as
-// many doubling steps as the longest run needs are taken (steps with a
-// larger offset add nothing to any run's last lane, so the totals are the
-// same bit for bit): every run is at most 2^k lanes long exactly when each
-// lane has a head among itself and its 2^k - 1 predecessors.
+// `heads`: every lane ends with the sum of its run up to itself (so the last
+// lane of a run holds the run's totals).  All lane moves are DPP, none goes
+// through LDS: doubling steps inside each 16-lane row (row_shr 1, 2, 4, 8),
+// then the rows' last lanes carried across (row_bcast 15, row_bcast 31) to
+// the lanes whose run began in an earlier row.  Only as many in-row steps
+// as the longest run needs are taken (every run is at most 2^k lanes long
+// exactly when each lane has a head among itself and its 2^k - 1
+// predecessors), and a carry only where a row's first lane is no head.
 template <int N>
 __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
   int steps = 0;
@@ -504,14 +507,34 @@ __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
   const int lane = lane_id();
   const uint64_t upto = lane == 63 ? heads : heads & ((2ull << lane) - 1ull);
   const int head = 63 - __clzll((long long)upto);
+  const int col = lane & 15, row0 = lane & ~15;
+  static_for<0, 4>([&](auto sc) {
+    constexpr int off = 1 << decltype(sc)::value;
+    if (decltype(sc)::value < steps) {
+      const bool take = col >= off && lane - off >= head;
 #pragma unroll
-  for (int s = 0; s < 6; ++s) {
-    if (s >= steps) break;
-    const int off = 1 << s;
+      for (int k = 0; k < N; ++k) {
+        const float t = row_shr<off>(v[k]);
+        if (take) v[k] += t;
+      }
+    }
+  });
+  // rows 1 and 3: lanes 15 and 47 hold their run's sum over rows 0 and 2
+  if (!((heads >> 16) & 1ull) || !((heads >> 48) & 1ull)) {
+    const bool take = ((lane >> 4) & 1) && head < row0;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      const float t = off == 1 ? wave_shr1(v[k]) : __shfl_up(v[k], off, 64);
-      if (lane - off >= head) v[k] += t;
+      const float t = row_bcast15(v[k]);
+      if (take) v[k] += t;
+    }
+  }
+  // rows 2 and 3: lane 31 holds its run's sum over rows 0 and 1
+  if (!((heads >> 32) & 1ull)) {
+    const bool take = lane >= 32 && head < 32;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const float t = row_bcast31(v[k]);
+      if (take) v[k] += t;
     }
   }
 }

@@ -48,6 +48,22 @@ __device__ __forceinline__ float wave_sum_dpp(float v) {
 // VALU move, no LDS crossbar).  Every lane of the wave must be active.
 __device__ __forceinline__ int wave_shr1(int x) { return __builtin_amdgcn_update_dpp(0, x, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ float wave_shr1(float x) { return __int_as_float(wave_shr1(__float_as_int(x))); }
+// DPP row_shr:N: lane l takes lane l - N of its own 16-lane row (0 where
+// that lies before the row's first lane).
+template <int N>
+__device__ __forceinline__ float row_shr(float x) {
+  static_assert(N >= 1 && N <= 15, "row shift");
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x110 + N, 0xf, 0xf, true));
+}
+// DPP row_bcast:15 and row_bcast:31: rows 1 and 3 take lanes 15 and 47
+// (the last lanes of rows 0 and 2); rows 2 and 3 take lane 31.  The other
+// rows read 0.
+__device__ __forceinline__ float row_bcast15(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x142, 0xa, 0xf, false));
+}
+__device__ __forceinline__ float row_bcast31(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x143, 0xc, 0xf, false));
+}
 
 // Totals of 8 per-lane values over the wave, transposed: lane l ends with
 // the total of value (l >> 1) & 7.  A butterfly over the lane bits inside
