@@ -160,31 +160,58 @@ __device__ __forceinline__ void static_for(F&& f) {
 template <int TB, int TO, int TI, bool ITMAJ, int IT0, int IT1, int ACC, int NWV>
 __device__ __forceinline__ void dw_tiles_range(const float* Xs, const float* Ys, v4f (&acc)[ACC], int w, int lane) {
   const int kk = lane >> 4, i = lane & 15;
-  static_for<0, TO * TI>([&](auto tc) {
-    constexpr int t = decltype(tc)::value;
-    constexpr int ot = tile_ot<TO, TI, ITMAJ>(t), it = tile_it<TO, TI, ITMAJ>(t);
-    constexpr int id = TB + t;
-    if constexpr (it >= IT0 && it < IT1) {
-      if (id % NWV == w) {
-        v4f c = acc[id / NWV];
-        // k runs over the staged points, 4 per MFMA, UB MFMAs per unrolled
-        // block (fewer with 8 waves, whose registers are capped at 256)
-        constexpr int KS = NWV * 16 / 4;
-        constexpr int UB = NWV >= 8 ? 1 : 8;
-        static_assert(KS % UB == 0, "staged points per round");
-        for (int s0 = 0; s0 < KS; s0 += UB) {
-#pragma unroll
-          for (int u = 0; u < UB; ++u) {
-            const int p = 4 * (s0 + u) + kk;
-            const float av = Ys[swz(p, 16 * ot + i)];
-            const float bv = Xs[swz(p, 16 * it + i)];
-            c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
-          }
-        }
-        acc[id / NWV] = c;
-      }
+  constexpr int KS = NWV * 16 / 4;   // MFMA k-steps over the staged points
+  // the layer's tile numbers [T0, T1) that hold the input tiles [IT0, IT1)
+  constexpr bool FULL = IT0 == 0 && IT1 == TI;
+  constexpr int T0 = FULL ? 0 : (ITMAJ ? IT0 * TO : -1);
+  constexpr int T1 = FULL ? TO * TI : (ITMAJ ? IT1 * TO : -1);
+  if constexpr (T0 >= 0 && TB % NWV == 0 && T0 % NWV == 0 && (T1 - T0) % NWV == 0) {
+    // every wave owns the same number of the range's tiles, t = w + NWV m,
+    // with accumulators acc[TB / NWV + m]: independent MFMA chains stepped
+    // together over k, so that they overlap each other and the operand reads
+    constexpr int M0 = T0 / NWV, NM = (T1 - T0) / NWV;
+    int ya[NM], xa[NM];
+    static_for<0, NM>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      const int t = w + NWV * (M0 + m);
+      ya[m] = 16 * tile_ot<TO, TI, ITMAJ>(t) + i;
+      xa[m] = 16 * tile_it<TO, TI, ITMAJ>(t) + i;
+    });
+#pragma unroll 4
+    for (int s = 0; s < KS; ++s) {
+      const int p = 4 * s + kk;
+      static_for<0, NM>([&](auto mc) {
+        constexpr int m = decltype(mc)::value;
+        v4f& c = acc[TB / NWV + M0 + m];
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[swz(p, ya[m])], Xs[swz(p, xa[m])], c, 0, 0, 0);
+      });
     }
-  });
+  } else {
+    static_for<0, TO * TI>([&](auto tc) {
+      constexpr int t = decltype(tc)::value;
+      constexpr int ot = tile_ot<TO, TI, ITMAJ>(t), it = tile_it<TO, TI, ITMAJ>(t);
+      constexpr int id = TB + t;
+      if constexpr (it >= IT0 && it < IT1) {
+        if (id % NWV == w) {
+          v4f c = acc[id / NWV];
+          // k runs over the staged points, 4 per MFMA, UB MFMAs per unrolled
+          // block (fewer with 8 waves, whose registers are capped at 256)
+          constexpr int UB = NWV >= 8 ? 1 : 8;
+          static_assert(KS % UB == 0, "staged points per round");
+          for (int s0 = 0; s0 < KS; s0 += UB) {
+#pragma unroll
+            for (int u = 0; u < UB; ++u) {
+              const int p = 4 * (s0 + u) + kk;
+              const float av = Ys[swz(p, 16 * ot + i)];
+              const float bv = Xs[swz(p, 16 * it + i)];
+              c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
+            }
+          }
+          acc[id / NWV] = c;
+        }
+      }
+    });
+  }
 }
 
 template <int TB, int TO, int TI, int ACC, int NWV>
