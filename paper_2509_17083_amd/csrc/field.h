@@ -108,18 +108,32 @@ template <int OT0, int OT1, int S, int K0, int K1>
 __device__ __forceinline__ void mfma_accum(const float* __restrict__ Wl, const float (&x)[S],
                                            v4f (&acc)[OT1 - OT0], int lane) {
   static_assert(K0 % 4 == 0 && K1 % 4 == 0 && 0 <= K0 && K0 <= K1 && K1 <= S, "k-step range");
+  constexpr int NO = OT1 - OT0;
+  // the next k-quad's weights are read while the current quad's MFMAs run
+  float4 w[2][NO];
+  if constexpr (K0 < K1) {
+#pragma unroll
+    for (int ot = OT0; ot < OT1; ++ot)
+      w[0][ot - OT0] = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + K0 / 4) * 64 + lane) * 4);
+  }
 #pragma unroll
   for (int sq = K0 / 4; sq < K1 / 4; ++sq) {
+    const int cur = (sq - K0 / 4) & 1;
+    if (sq + 1 < K1 / 4) {
+#pragma unroll
+      for (int ot = OT0; ot < OT1; ++ot)
+        w[cur ^ 1][ot - OT0] = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq + 1) * 64 + lane) * 4);
+    }
 #pragma unroll
     for (int ot = OT0; ot < OT1; ++ot) {
-      const float4 w = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq) * 64 + lane) * 4);
+      const float4 wv = w[cur][ot - OT0];
       v4f& c = acc[ot - OT0];
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.x, x[4 * sq + 0], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.y, x[4 * sq + 1], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.z, x[4 * sq + 2], c, 0, 0, 0);
-      c = __builtin_amdgcn_mfma_f32_16x16x4f32(w.w, x[4 * sq + 3], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.x, x[4 * sq + 0], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.y, x[4 * sq + 1], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, x[4 * sq + 2], c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, x[4 * sq + 3], c, 0, 0, 0);
     }
-    // keep the weight reads of one k-quad in flight at a time (register budget)
+    // at most two k-quads of weight reads in flight (register budget)
     asm volatile("" ::: "memory");
   }
 }
@@ -232,16 +246,29 @@ template <int OT0, int OT1, int S, int K0, int K1>
 __device__ __forceinline__ void mfma_accum_bf16(const __bf16* __restrict__ Wl, const float (&x)[S],
                                                 v4f (&acc)[OT1 - OT0], int lane) {
   static_assert(S % 8 == 0 && K0 % 8 == 0 && K1 % 8 == 0 && 0 <= K0 && K0 <= K1 && K1 <= S, "bf16 k-step range");
+  constexpr int NO = OT1 - OT0;
+  // the next k-step's weights are read while the current step's MFMAs run
+  v8bf w[2][NO];
+  if constexpr (K0 < K1) {
+#pragma unroll
+    for (int ot = OT0; ot < OT1; ++ot)
+      w[0][ot - OT0] = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + K0 / 8) * 64 + lane) * 8);
+  }
 #pragma unroll
   for (int q = K0 / 8; q < K1 / 8; ++q) {
+    const int cur = (q - K0 / 8) & 1;
+    if (q + 1 < K1 / 8) {
+#pragma unroll
+      for (int ot = OT0; ot < OT1; ++ot)
+        w[cur ^ 1][ot - OT0] = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + q + 1) * 64 + lane) * 8);
+    }
     v8bf b;
 #pragma unroll
     for (int e = 0; e < 8; ++e) b[e] = (__bf16)x[8 * q + e];
 #pragma unroll
-    for (int ot = OT0; ot < OT1; ++ot) {
-      const v8bf w = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + q) * 64 + lane) * 8);
-      acc[ot - OT0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, b, acc[ot - OT0], 0, 0, 0);
-    }
+    for (int ot = OT0; ot < OT1; ++ot)
+      acc[ot - OT0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[cur][ot - OT0], b, acc[ot - OT0], 0, 0, 0);
+    // at most two k-steps of weight reads in flight (register budget)
     asm volatile("" ::: "memory");
   }
 }
