@@ -124,6 +124,11 @@ __device__ __forceinline__ void mfma_accum(const float* __restrict__ Wl, const f
       for (int ot = OT0; ot < OT1; ++ot)
         w[cur ^ 1][ot - OT0] = *reinterpret_cast<const float4*>(Wl + ((ot * (S / 4) + sq + 1) * 64 + lane) * 4);
     }
+    // the reads above issue before this k-quad's MFMAs (a scheduling
+    // barrier: the scheduler would otherwise sink them below), and no later
+    // read moves above them, so at most two k-quads of weights are in
+    // flight (register budget)
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int ot = OT0; ot < OT1; ++ot) {
       const float4 wv = w[cur][ot - OT0];
@@ -133,8 +138,6 @@ __device__ __forceinline__ void mfma_accum(const float* __restrict__ Wl, const f
       c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.z, x[4 * sq + 2], c, 0, 0, 0);
       c = __builtin_amdgcn_mfma_f32_16x16x4f32(wv.w, x[4 * sq + 3], c, 0, 0, 0);
     }
-    // at most two k-quads of weight reads in flight (register budget)
-    asm volatile("" ::: "memory");
   }
 }
 
@@ -262,14 +265,15 @@ __device__ __forceinline__ void mfma_accum_bf16(const __bf16* __restrict__ Wl, c
       for (int ot = OT0; ot < OT1; ++ot)
         w[cur ^ 1][ot - OT0] = *reinterpret_cast<const v8bf*>(Wl + ((ot * (S / 8) + q + 1) * 64 + lane) * 8);
     }
+    // the reads above issue before this k-step's MFMAs (scheduling
+    // barrier); at most two k-steps of weights in flight (register budget)
+    __builtin_amdgcn_sched_barrier(0);
     v8bf b;
 #pragma unroll
     for (int e = 0; e < 8; ++e) b[e] = (__bf16)x[8 * q + e];
 #pragma unroll
     for (int ot = OT0; ot < OT1; ++ot)
       acc[ot - OT0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[cur][ot - OT0], b, acc[ot - OT0], 0, 0, 0);
-    // at most two k-steps of weight reads in flight (register budget)
-    asm volatile("" ::: "memory");
   }
 }
 
