@@ -177,13 +177,30 @@ __device__ __forceinline__ void dw_tiles_range(const float* Xs, const float* Ys,
       ya[m] = 16 * tile_ot<TO, TI, ITMAJ>(t) + i;
       xa[m] = 16 * tile_it<TO, TI, ITMAJ>(t) + i;
     });
-#pragma unroll 4
+    // operands of k-step s + 1 are read before the MFMAs of step s (a
+    // scheduling barrier between them keeps the reads ahead)
+    float av[2][NM], bv[2][NM];
+    static_for<0, NM>([&](auto mc) {
+      constexpr int m = decltype(mc)::value;
+      av[0][m] = Ys[swz(kk, ya[m])];
+      bv[0][m] = Xs[swz(kk, xa[m])];
+    });
+#pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int p = 4 * s + kk;
+      const int cur = s & 1;
+      if (s + 1 < KS) {
+        const int p = 4 * (s + 1) + kk;
+        static_for<0, NM>([&](auto mc) {
+          constexpr int m = decltype(mc)::value;
+          av[cur ^ 1][m] = Ys[swz(p, ya[m])];
+          bv[cur ^ 1][m] = Xs[swz(p, xa[m])];
+        });
+      }
+      __builtin_amdgcn_sched_barrier(0);
       static_for<0, NM>([&](auto mc) {
         constexpr int m = decltype(mc)::value;
         v4f& c = acc[TB / NWV + M0 + m];
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(Ys[swz(p, ya[m])], Xs[swz(p, xa[m])], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(av[cur][m], bv[cur][m], c, 0, 0, 0);
       });
     }
   } else {
@@ -193,21 +210,33 @@ __device__ __forceinline__ void dw_tiles_range(const float* Xs, const float* Ys,
       constexpr int id = TB + t;
       if constexpr (it >= IT0 && it < IT1) {
         if (id % NWV == w) {
-          v4f c = acc[id / NWV];
-          // k runs over the staged points, 4 per MFMA, UB MFMAs per unrolled
-          // block (fewer with 8 waves, whose registers are capped at 256)
-          constexpr int UB = NWV >= 8 ? 1 : 8;
-          static_assert(KS % UB == 0, "staged points per round");
-          for (int s0 = 0; s0 < KS; s0 += UB) {
+          // k runs over the staged points, 4 per MFMA, in four partial sums
+          // (independent MFMA chains); the operands of the next four k-steps
+          // are read before the MFMAs of the current four
+          static_assert(KS % 4 == 0, "staged points per round");
+          v4f c[4] = {acc[id / NWV], v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+          float av[2][4], bv[2][4];
 #pragma unroll
-            for (int u = 0; u < UB; ++u) {
-              const int p = 4 * (s0 + u) + kk;
-              const float av = Ys[swz(p, 16 * ot + i)];
-              const float bv = Xs[swz(p, 16 * it + i)];
-              c = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv, c, 0, 0, 0);
-            }
+          for (int u = 0; u < 4; ++u) {
+            av[0][u] = Ys[swz(4 * u + kk, 16 * ot + i)];
+            bv[0][u] = Xs[swz(4 * u + kk, 16 * it + i)];
           }
-          acc[id / NWV] = c;
+#pragma unroll
+          for (int q = 0; q < KS / 4; ++q) {
+            const int cur = q & 1;
+            if (q + 1 < KS / 4) {
+#pragma unroll
+              for (int u = 0; u < 4; ++u) {
+                const int p = 4 * (4 * (q + 1) + u) + kk;
+                av[cur ^ 1][u] = Ys[swz(p, 16 * ot + i)];
+                bv[cur ^ 1][u] = Xs[swz(p, 16 * it + i)];
+              }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int u = 0; u < 4; ++u) c[u] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[cur][u], bv[cur][u], c[u], 0, 0, 0);
+          }
+          acc[id / NWV] = (c[0] + c[1]) + (c[2] + c[3]);
         }
       }
     });
