@@ -760,6 +760,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
     float pxf = 0.f, pyf = 0.f, pzf = 0.f;
     int gi = 0, v_r = 0, pix = 0;
     float dfr[Sh::FPL], dxg[D::SG];
+    float dgeo_in[4] = {0.f, 0.f, 0.f, 0.f}, rot_in[4] = {0.f, 0.f, 0.f, 0.f}, dcol_in[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < Sh::FPL; ++s) dfr[s] = 0.f;
 #pragma unroll
@@ -779,6 +780,19 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         fg[2 * k] = vg.x; fg[2 * k + 1] = vg.y;
         fr[2 * k] = vr.x; fr[2 * k + 1] = vr.y;
       }
+      // the output gradients of both decoders (view 0) and the explicit
+      // rotation are read here, so that their latency hides under the
+      // forward recomputation (the MFMA layers' scheduling barriers keep
+      // later reads from moving up); rows of item 0 for an invalid lane
+      {
+        const int itc = valid ? item : 0;
+        const float4 d4 = *reinterpret_cast<const float4*>(a.dgeo + (size_t)itc * 8 + 4 * (g & 1));
+        dgeo_in[0] = d4.x; dgeo_in[1] = d4.y; dgeo_in[2] = d4.z; dgeo_in[3] = d4.w;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) rot_in[k] = a.rot_e ? a.rot_e[(size_t)k * a.n + gi] : 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dcol_in[c] = a.dcol[(size_t)itc * V * 3 + c];
+      }
       // ---- geometry decoder adjoint
       float x1g[D::SG];
 #pragma unroll
@@ -787,16 +801,13 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       v4f og;
       D::template fwd<D::SG>(s_wf_geo, x1g, hg, og, lane);
       v4f dg = v4f{0.f, 0.f, 0.f, 0.f};
-      if (valid && g == 0) {
-        const float* d = a.dgeo + (size_t)item * 8;
-        dg = v4f{d[0], d[1], d[2], d[3]};
-      }
+      if (valid && g == 0) dg = v4f{dgeo_in[0], dgeo_in[1], dgeo_in[2], dgeo_in[3]};
       if (valid && g == 1) {
         // rotation rows: q = r / |r| with r = r_n (+ r_e)
-        const float* d = a.dgeo + (size_t)item * 8 + 4;
+        const float* d = dgeo_in;
         float r[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) r[k] = og[k] + (a.rot_e ? a.rot_e[(size_t)k * a.n + gi] : 0.f);
+        for (int k = 0; k < 4; ++k) r[k] = og[k] + rot_in[k];
         const float nr = sqrtf((r[0] * r[0] + r[1] * r[1]) + (r[2] * r[2] + r[3] * r[3]));
         const float inr = 1.f / nr;
         float q[4], qd = 0.f;
@@ -863,6 +874,16 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       for (int k = 0; k < Sh::S_HID; ++k) dh_sum[k] = 0.f;
     }
     for (int v = 0; v < nviews; ++v) {
+      // Gaussians: the next view's colour gradient is read ahead (the
+      // current view's arrived during the previous view or the round start)
+      float dcol_next[3] = {0.f, 0.f, 0.f};
+      if constexpr (!RAY) {
+        if (v + 1 < nviews) {
+          const int itc = valid ? item : 0;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) dcol_next[c] = a.dcol[((size_t)itc * V + v + 1) * 3 + c];
+        }
+      }
       float dir[3];
       float inv_len = 0.f;
       if constexpr (!RAY) {
@@ -893,8 +914,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       v4f dc = v4f{0.f, 0.f, 0.f, 0.f};
       if (valid && g == 0) {
         if constexpr (!RAY) {
-          const float* d = a.dcol + ((size_t)item * V + v) * 3;
-          dc = v4f{d[0], d[1], d[2], 0.f};
+          dc = v4f{dcol_in[0], dcol_in[1], dcol_in[2], 0.f};
         } else {
           const int rem = pix - v_r * HW;
           const float T = a.T_final[pix];
@@ -927,6 +947,8 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         const float dot = dir[0] * dd[0] + dir[1] * dd[1] + dir[2] * dd[2];
 #pragma unroll
         for (int k = 0; k < 3; ++k) dp_dir[k] += (dd[k] - dir[k] * dot) * inv_len;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) dcol_in[c] = dcol_next[c];
       }
     }
     if (shared) {
