@@ -858,6 +858,24 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         for (int s = 0; s < Sh::FPL; ++s) fr[s] = 0.f;
       }
     }
+    // Gaussians: the saved feature derivatives this lane combines at the
+    // end of the round are read before the colour decoder's adjoint, whose
+    // work hides their latency
+    float jv[RAY ? 1 : Sh::L / 4][12];
+    if constexpr (!RAY) {
+      if (a.jac) {
+        const int itc = valid ? item : 0;
+#pragma unroll
+        for (int k = 0; k < Sh::L / 4; ++k) {
+          const float4* J4 = reinterpret_cast<const float4*>(a.jac + ((size_t)itc * Sh::L + g + 4 * k) * 12);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            const float4 t = J4[q];
+            jv[k][4 * q] = t.x; jv[k][4 * q + 1] = t.y; jv[k][4 * q + 2] = t.z; jv[k][4 * q + 3] = t.w;
+          }
+        }
+      }
+    }
     // ---- colour decoder adjoint, once per view (one pass in ray mode).
     // With several views the first layer's radiance-feature part is shared
     // (Eq. 6): formed once forward, its adjoint once after the views.
@@ -974,10 +992,8 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       if (a.jac && valid) {
 #pragma unroll
         for (int k = 0; k < Sh::L / 4; ++k) {
-          const float4* J4 = reinterpret_cast<const float4*>(a.jac + ((size_t)item * Sh::L + g + 4 * k) * 12);
-          const float4 j0 = J4[0], j1 = J4[1], j2 = J4[2];
-          const float Jg[6] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y};
-          const float Jr[6] = {j1.z, j1.w, j2.x, j2.y, j2.z, j2.w};
+          const float* Jg = jv[k];       // d(geometry features)/dx, 2 x 3
+          const float* Jr = jv[k] + 6;   // d(radiance features)/dx, 2 x 3
 #pragma unroll
           for (int d = 0; d < 3; ++d)
             dxv[d] += (dxg[2 * k] * Jg[d] + dxg[2 * k + 1] * Jg[3 + d]) +
