@@ -761,6 +761,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
     int gi = 0, v_r = 0, pix = 0;
     float dfr[Sh::FPL], dxg[D::SG];
     float dgeo_in[4] = {0.f, 0.f, 0.f, 0.f}, rot_in[4] = {0.f, 0.f, 0.f, 0.f}, dcol_in[3] = {0.f, 0.f, 0.f};
+    float bg_T = 0.f, bg_dL[3] = {0.f, 0.f, 0.f};
 #pragma unroll
     for (int s = 0; s < Sh::FPL; ++s) dfr[s] = 0.f;
 #pragma unroll
@@ -848,7 +849,17 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
           fr[2 * k] = f2.x;
           fr[2 * k + 1] = f2.y;
         }
-      } else {
+      }
+      // the pixel's final transmittance and dL/dC, read here so that their
+      // latency hides under the forward recomputation (every lane reads
+      // them; the lanes of group 0 use them)
+      {
+        const int rem = pix - v_r * HW;
+        bg_T = a.T_final[pix];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bg_dL[c] = a.dL[((size_t)v_r * 3 + c) * HW + rem];
+      }
+      if constexpr (!SAVED) {
         gather_lane<Sh::L, false, TT>(a.grid, x, g, nullptr, (const TT*)a.table_rad, fg, fr, nullptr, nullptr);
       }
       const double dn = sqrt((d[0] * d[0] + d[1] * d[1]) + d[2] * d[2]);
@@ -934,12 +945,10 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         if constexpr (!RAY) {
           dc = v4f{dcol_in[0], dcol_in[1], dcol_in[2], 0.f};
         } else {
-          const int rem = pix - v_r * HW;
-          const float T = a.T_final[pix];
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
             const float cs = sigmoidf_(oc4[c]);
-            dc[c] = T * a.dL[((size_t)v_r * 3 + c) * HW + rem] * cs * (1.f - cs);
+            dc[c] = bg_T * bg_dL[c] * cs * (1.f - cs);
           }
         }
       }
