@@ -1067,29 +1067,53 @@ __global__ __launch_bounds__(256) void k_grid_scatter(GridBwdArgs a) {
   const uint32_t Tg = a.grid.mask_geo + 1u, Tr = a.grid.mask_rad + 1u;
   const bool single = a.grid.single != 0;
   const bool do_geo = a.g_table_geo && !single;
-  for (int lev = 0; lev < a.grid.L; ++lev) {
-    const int res = a.grid.res[lev];
-    int ci[3];
-    float wv[3];
-    grid_cell(x, res, ci, wv);
-    const uint32_t side = (uint32_t)res + 1u;
-    float2 dg = make_float2(0.f, 0.f), dr = dg;
-    if (valid) {
-      dg = *reinterpret_cast<const float2*>(a.dfeat_geo + (size_t)item * 2 * a.grid.L + 2 * lev);
-      dr = *reinterpret_cast<const float2*>(a.dfeat_rad + (size_t)item * 2 * a.grid.L + 2 * lev);
+  // every level's feature gradients are read before the first atomic: a
+  // wave's memory counter completes in issue order, so a read issued after
+  // a level's atomics would wait for all of them.  Two levels per float4;
+  // the pairs shift down one register slot per step of the (rolled) loop
+  // over level pairs, so that no register array is indexed at run time.
+  float4 fgeo[GRID_MAX_LEVELS / 2], frad[GRID_MAX_LEVELS / 2];
+  const int itc = valid ? item : 0;
+#pragma unroll
+  for (int k = 0; k < GRID_MAX_LEVELS / 2; ++k) {
+    fgeo[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+    frad[k] = fgeo[k];
+    if (valid && 2 * k < a.grid.L) {
+      fgeo[k] = *reinterpret_cast<const float4*>(a.dfeat_geo + (size_t)itc * 2 * a.grid.L + 4 * k);
+      frad[k] = *reinterpret_cast<const float4*>(a.dfeat_rad + (size_t)itc * 2 * a.grid.L + 4 * k);
     }
-    if (single) {
-      // one field read by both decoders: its feature gradient is the sum
-      dr.x += dg.x;
-      dr.y += dg.y;
+  }
+  for (int lp = 0; lp < a.grid.L; lp += 2) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int lev = lp + h;
+      if (lev < a.grid.L) {
+        const int res = a.grid.res[lev];
+        int ci[3];
+        float wv[3];
+        grid_cell(x, res, ci, wv);
+        const uint32_t side = (uint32_t)res + 1u;
+        float2 dg = h ? make_float2(fgeo[0].z, fgeo[0].w) : make_float2(fgeo[0].x, fgeo[0].y);
+        float2 dr = h ? make_float2(frad[0].z, frad[0].w) : make_float2(frad[0].x, frad[0].y);
+        if (single) {
+          // one field read by both decoders: its feature gradient is the sum
+          dr.x += dg.x;
+          dr.y += dg.y;
+        }
+        const uint64_t heads = cell_heads(ci);
+        if (do_geo)
+          scatter_level<false>(a.g_table_geo + (size_t)lev * Tg * 2, heads, ci, wv, dg, (a.grid.dense_geo >> lev) & 1u,
+                               side, a.grid.mask_geo, st);
+        if (a.g_table_rad)
+          scatter_level<false>(a.g_table_rad + (size_t)lev * Tr * 2, heads, ci, wv, dr, (a.grid.dense_rad >> lev) & 1u,
+                               side, a.grid.mask_rad, st);
+      }
     }
-    const uint64_t heads = cell_heads(ci);
-    if (do_geo)
-      scatter_level<false>(a.g_table_geo + (size_t)lev * Tg * 2, heads, ci, wv, dg, (a.grid.dense_geo >> lev) & 1u, side,
-                    a.grid.mask_geo, st);
-    if (a.g_table_rad)
-      scatter_level<false>(a.g_table_rad + (size_t)lev * Tr * 2, heads, ci, wv, dr, (a.grid.dense_rad >> lev) & 1u, side,
-                    a.grid.mask_rad, st);
+#pragma unroll
+    for (int k = 0; k + 1 < GRID_MAX_LEVELS / 2; ++k) {
+      fgeo[k] = fgeo[k + 1];
+      frad[k] = frad[k + 1];
+    }
   }
 }
 

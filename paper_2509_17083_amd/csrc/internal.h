@@ -43,9 +43,11 @@ struct Cams {
   int V;
 };
 
+constexpr int GRID_MAX_LEVELS = 16;
+
 struct GridP {
   int L;                 // levels
-  int res[16];           // N_l
+  int res[GRID_MAX_LEVELS];   // N_l
   uint32_t dense_geo;    // bit l set: level l of the geometry table is dense
   uint32_t dense_rad;
   uint32_t mask_geo;     // T_geo - 1
