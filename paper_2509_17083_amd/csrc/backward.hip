@@ -768,19 +768,19 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
     for (int s = 0; s < D::SG; ++s) dxg[s] = 0.f;
     float dp_dir[3] = {0.f, 0.f, 0.f};
     if constexpr (!RAY) {
-      gi = valid ? a.vis_idx[item] : a.vis_idx[0];
-      pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
+      // the features (indexed by the list position) are read before the
+      // Gaussian's index, whose wait then covers them too
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
-        float2 vg = make_float2(0.f, 0.f), vr = vg;
-        if (valid) {
-          vg = *reinterpret_cast<const float2*>(a.feat_geo + (size_t)item * 2 * Sh::L + 2 * lev);
-          vr = *reinterpret_cast<const float2*>(a.feat_rad + (size_t)item * 2 * Sh::L + 2 * lev);
-        }
-        fg[2 * k] = vg.x; fg[2 * k + 1] = vg.y;
-        fr[2 * k] = vr.x; fr[2 * k + 1] = vr.y;
+        const int itc = valid ? item : 0;
+        const float2 vg = *reinterpret_cast<const float2*>(a.feat_geo + (size_t)itc * 2 * Sh::L + 2 * lev);
+        const float2 vr = *reinterpret_cast<const float2*>(a.feat_rad + (size_t)itc * 2 * Sh::L + 2 * lev);
+        fg[2 * k] = valid ? vg.x : 0.f; fg[2 * k + 1] = valid ? vg.y : 0.f;
+        fr[2 * k] = valid ? vr.x : 0.f; fr[2 * k + 1] = valid ? vr.y : 0.f;
       }
+      gi = valid ? a.vis_idx[item] : a.vis_idx[0];
+      pxf = a.pos[gi]; pyf = a.pos[a.n + gi]; pzf = a.pos[2 * a.n + gi];
       // the output gradients of both decoders (view 0) and the explicit
       // rotation are read here, so that their latency hides under the
       // forward recomputation (the MFMA layers' scheduling barriers keep
@@ -821,9 +821,15 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
 #pragma unroll
         for (int k = 0; k < 4; ++k) dr[k] = (d[k] - q[k] * qd) * inr;
         dg = v4f{dr[0], dr[1], dr[2], dr[3]};
-        if (a.g_rot_e && a.rot_e)
+        if (a.g_rot_e && a.rot_e) {
+          // the four reads first (the compiler cannot tell the rows apart,
+          // so an interleaved read-add-write would serialise them)
+          float cur[4];
 #pragma unroll
-          for (int k = 0; k < 4; ++k) a.g_rot_e[(size_t)k * a.n + gi] += dr[k];
+          for (int k = 0; k < 4; ++k) cur[k] = a.g_rot_e[(size_t)k * a.n + gi];
+#pragma unroll
+          for (int k = 0; k < 4; ++k) a.g_rot_e[(size_t)k * a.n + gi] = cur[k] + dr[k];
+        }
       }
       D::template bwd<false, D::SG, ACC, NWV>(s_wb_geo, x1g, hg, dg, dxg, Xs, Ys, accW, w, lane);
     } else {
@@ -1019,8 +1025,11 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       if (valid && g == 0 && a.g_pos) {
         float dpw[3] = {0.f, 0.f, 0.f};
         if (a.jac) contract_vjp(a.grid, pxf, pyf, pzf, dxv, dpw);
+        float cur[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp_dir[k] + dpw[k];
+        for (int k = 0; k < 3; ++k) cur[k] = a.g_pos[(size_t)k * a.n + gi];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] = cur[k] + (dp_dir[k] + dpw[k]);
       }
     } else if (a.g_table_rad) {
       // background points: the round's feature gradients to LDS (the dW
@@ -1205,8 +1214,11 @@ __global__ __launch_bounds__(256) void k_grid_bwd(GridBwdArgs a) {
   if (valid && a.g_pos) {
     float dp[3];
     contract_vjp(a.grid, pxf, pyf, pzf, dxv, dp);
+    float cur[3];
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] += dp[k];
+    for (int k = 0; k < 3; ++k) cur[k] = a.g_pos[(size_t)k * a.n + gi];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * a.n + gi] = cur[k] + dp[k];
   }
 }
 
