@@ -272,25 +272,42 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
                            qw * dRq[2][0] + qz * dRq[2][1] - 2.f * qy * dRq[2][2]);
   const float dqz = 2.f * (-2.f * qz * dRq[0][0] - qw * dRq[0][1] + qx * dRq[0][2] + qw * dRq[1][0] - 2.f * qz * dRq[1][1] +
                            qy * dRq[1][2] + qx * dRq[2][0] + qy * dRq[2][1]);
-  if (a.dens_accum) {
-    a.dens_accum[gi] += dens_g;
-    a.dens_count[gi] += dens_n;
-  }
   const float do_pre = do_sum * op * (1.f - op);
   float* dg = a.dgeo + (size_t)s * 8;
   dg[0] = do_pre;
   dg[1] = ds_pre[0]; dg[2] = ds_pre[1]; dg[3] = ds_pre[2];
   dg[4] = dqw; dg[5] = dqx; dg[6] = dqy; dg[7] = dqz;
+  // the gradient accumulators: every read first, then every write (the
+  // compiler cannot tell the arrays apart, so interleaved read-add-writes
+  // would each wait for the previous one)
+  float cur[12];
+#pragma unroll
+  for (int k = 0; k < 12; ++k) cur[k] = 0.f;
+  if (a.dens_accum) { cur[0] = a.dens_accum[gi]; cur[1] = a.dens_count[gi]; }
   if (a.g_pos)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * n + gi] += dpos[k];
-  if (a.g_opac_e) a.g_opac_e[gi] += do_pre;
+    for (int k = 0; k < 3; ++k) cur[2 + k] = a.g_pos[(size_t)k * n + gi];
+  if (a.g_opac_e) cur[5] = a.g_opac_e[gi];
   if (a.g_scale_e)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.g_scale_e[(size_t)k * n + gi] += ds_pre[k];
+    for (int k = 0; k < 3; ++k) cur[6 + k] = a.g_scale_e[(size_t)k * n + gi];
   if (a.g_col_e)
 #pragma unroll
-    for (int k = 0; k < 3; ++k) a.g_col_e[(size_t)k * n + gi] += dce[k];
+    for (int k = 0; k < 3; ++k) cur[9 + k] = a.g_col_e[(size_t)k * n + gi];
+  if (a.dens_accum) {
+    a.dens_accum[gi] = cur[0] + dens_g;
+    a.dens_count[gi] = cur[1] + dens_n;
+  }
+  if (a.g_pos)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_pos[(size_t)k * n + gi] = cur[2 + k] + dpos[k];
+  if (a.g_opac_e) a.g_opac_e[gi] = cur[5] + do_pre;
+  if (a.g_scale_e)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_scale_e[(size_t)k * n + gi] = cur[6 + k] + ds_pre[k];
+  if (a.g_col_e)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.g_col_e[(size_t)k * n + gi] = cur[9 + k] + dce[k];
 }
 
 // ---------------------------------------------------------------- fields
