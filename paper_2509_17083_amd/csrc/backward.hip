@@ -495,8 +495,13 @@ static_assert(sizeof(CellStage) <= 4096, "cell stage size");
 // Word of corner c (feature 0; feature 1 follows) of staged cell `slot`.
 __device__ __forceinline__ int stage_at(int slot, int c) { return slot * 16 + 4 * ((c >> 1) ^ (slot & 3)) + 2 * (c & 1); }
 
+// Order of LDS accesses between the lanes of one wave (staging writes, then
+// other lanes' reads, then rewrites).  The LDS performs one wave's
+// operations in issue order, so a compiler fence that keeps the program
+// order suffices; no wait for the counter is needed (a loaded value is
+// still waited for where it is used).
 __device__ __forceinline__ void wave_lds_sync() {
-  asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+  asm volatile("" ::: "memory");
   __builtin_amdgcn_wave_barrier();
 }
 
