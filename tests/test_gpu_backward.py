@@ -184,6 +184,38 @@ def test_background_adjoint_saved_and_gathered_features_agree():
         assert float(g_saved["table_rad"].abs().max()) > 0
 
 
+def test_backward_in_spatial_order_changes_only_rounding():
+    """The Gaussians stored in Morton order (the benchmark's layout) give the
+    gradients of the seeded order, permuted, up to the order of the float
+    atomics.  In spatial order consecutive lanes share grid cells at the
+    coarse levels, so the Gaussian table scatter sums runs of lanes that
+    cross the 16- and 32-lane row boundaries before its atomics, where the
+    seeded order gives runs of about one lane."""
+    P = _P()
+    cfg, scene, cams = make("c100k", table_init=1.0, n_gauss=20000)
+    ds = device_scene(scene)
+    perm = ds.spatial_order()
+    inv = torch.empty_like(perm)
+    inv[perm] = torch.arange(perm.numel(), device=perm.device)
+    dsr = ds.reordered(perm)
+    H, W = cams[0].height, cams[0].width
+    dL = torch.from_numpy(hi.make_target_image((1, 3, H, W), seed=31) - 0.5).cuda()
+    st_a = P.render(ds, cams, P.TRAIN)
+    g_a = P.render_backward(ds, cams, st_a, dL, overlap=False)
+    st_b = P.render(dsr, cams, P.TRAIN)
+    g_b = P.render_backward(dsr, cams, st_b, dL, overlap=False)
+    torch.cuda.synchronize()
+    err = float((st_a.image - st_b.image).abs().max())
+    print("image max difference", err, flush=True)
+    assert err <= 1e-5
+    for k in ("pos", "scale_e", "rot_e", "opac_e", "col_e", "table_geo", "table_rad", "mlp_geo", "mlp_col"):
+        a = g_a[k]
+        b = g_b[k][..., inv] if k in ("pos", "scale_e", "rot_e", "opac_e", "col_e") else g_b[k]
+        rel = float((a - b).norm() / a.norm())
+        print(k, "spatial vs seeded order relative L2", rel, flush=True)
+        assert rel < 1e-5, (k, rel)
+
+
 def test_staged_backward_equals_one_call():
     P = _P()
     cfg, scene, cams = make("tiny", table_init=1.0)
