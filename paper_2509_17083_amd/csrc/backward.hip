@@ -684,7 +684,8 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
 // work as 2 halves of 64 consecutive pixels x 4 level groups (levels
 // lg, lg + 4, ...).  The pixels' contracted sphere points (float64, the
 // same cells as the forward gather) come from LDS too.  The atomics do not
-// return: they drain while the next round's MFMA work runs.
+// return; the wave's next global read waits for them (its memory counter
+// completes in issue order).
 constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
 
 template <int L, bool MERGE>
