@@ -658,7 +658,8 @@ hyrf_status hyrf_spatial_order(const hyrf_fields* fields, const float* pos, int3
     g.center[d] = fields->aabb_center[d];
     g.inv_half[d] = fields->aabb_inv_half[d];
   }
-  launch_order(pos, n, g, perm, ws, (hipStream_t)stream);
+  const hipError_t e = launch_order(pos, n, g, perm, ws, (hipStream_t)stream);
+  if (e != hipSuccess) return launch_error(e);
   return check_launch();
 }
 

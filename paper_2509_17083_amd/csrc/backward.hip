@@ -988,7 +988,9 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       // before the adjoint's first staging write
       if constexpr (RAY) __syncthreads();
       if (shared) {
-        D::template col_bwd_view<ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, dh_sum, Xs, Ys, accW, w, lane);
+        // background points never share (and their dW tiles are numbered
+        // without the geometry decoder's): not instantiated for them
+        if constexpr (!RAY) D::template col_bwd_view<ACC, NWV>(s_wb_col, x1c, hc, dc, dxc, dh_sum, Xs, Ys, accW, w, lane);
       } else {
         D::template bwd<true, D::SC, ACC, NWV, CB>(s_wb_col, x1c, hc, dc, dxc, Xs, Ys, accW, w, lane);
 #pragma unroll

@@ -303,22 +303,25 @@ __device__ __forceinline__ const float* mlp_backward_upper(const float* __restri
       for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[Sh::NH - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
   }
   const float* W = Wb + Sh::NT * 4 * 64;
-  // ---- hidden layers, last to first (only NH == 2: one W_2)
+  // ---- hidden layers, last to first (only NH == 2: one W_2); not
+  // instantiated for one hidden layer, whose tile numbers end before them
+  if constexpr (Sh::NH >= 2) {
 #pragma unroll
-  for (int k = Sh::NH - 1; k >= 1; --k) {
-    stage_units<Sh::S_HID>(Ys, pt, g, dh);
-    stage_units<Sh::S_HID>(Xs, pt, g, h[k - 1]);
-    __syncthreads();
-    constexpr int TB_H = TB0 + Sh::NT * TI1;
-    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
-    __syncthreads();
-    v4f acc[Sh::NT];
-    mfma_layer<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
-    W += Sh::NT * Sh::S_HID * 64;
+    for (int k = Sh::NH - 1; k >= 1; --k) {
+      stage_units<Sh::S_HID>(Ys, pt, g, dh);
+      stage_units<Sh::S_HID>(Xs, pt, g, h[k - 1]);
+      __syncthreads();
+      constexpr int TB_H = TB0 + Sh::NT * TI1;
+      dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
+      __syncthreads();
+      v4f acc[Sh::NT];
+      mfma_layer<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
+      W += Sh::NT * Sh::S_HID * 64;
 #pragma unroll
-    for (int b = 0; b < Sh::NT; ++b)
+      for (int b = 0; b < Sh::NT; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+        for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+    }
   }
   return W;
 }
@@ -478,21 +481,23 @@ __device__ __forceinline__ const __bf16* mlp_backward_upper_bf16(const __bf16* _
       for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[Sh::NH - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
   }
   const __bf16* W = Wb + Sh::NT * 8 * 64;
+  if constexpr (Sh::NH >= 2) {   // hidden layers, as in the float32 version
 #pragma unroll
-  for (int k = Sh::NH - 1; k >= 1; --k) {
-    stage_units<Sh::S_HID, true>(Ys, pt, g, dh);
-    stage_units<Sh::S_HID, true>(Xs, pt, g, h[k - 1]);
-    __syncthreads();
-    constexpr int TB_H = TB0 + Sh::NT * TI1;
-    dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
-    __syncthreads();
-    v4f acc[Sh::NT];
-    mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
-    W += Sh::NT * Sh::S_HID * 64;
+    for (int k = Sh::NH - 1; k >= 1; --k) {
+      stage_units<Sh::S_HID, true>(Ys, pt, g, dh);
+      stage_units<Sh::S_HID, true>(Xs, pt, g, h[k - 1]);
+      __syncthreads();
+      constexpr int TB_H = TB0 + Sh::NT * TI1;
+      dw_tiles<TB_H, Sh::NT, Sh::HID / 16, ACC, NWV>(Xs, Ys, accW, w, lane);
+      __syncthreads();
+      v4f acc[Sh::NT];
+      mfma_layer_bf16<Sh::NT, Sh::S_HID>(W, dh, acc, lane);
+      W += Sh::NT * Sh::S_HID * 64;
 #pragma unroll
-    for (int b = 0; b < Sh::NT; ++b)
+      for (int b = 0; b < Sh::NT; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+        for (int r = 0; r < 4; ++r) dh[4 * b + r] = h[k - 1][4 * b + r] > 0.f ? acc[b][r] : 0.f;
+    }
   }
   return W;
 }

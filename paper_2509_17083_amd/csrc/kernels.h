@@ -44,7 +44,7 @@ int radix_sort_pairs(uint32_t* k[2], uint32_t* v[2], int start, int64_t n, int b
 
 // ---- order.hip
 size_t order_ws_bytes(int n);
-void launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st);
+hipError_t launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st);
 
 // ---- quant.hip
 size_t quant_ws_elems(int levels, int log2_T);

@@ -36,13 +36,13 @@ size_t order_ws_bytes(int n) {
   return c.off;
 }
 
-void launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st) {
+hipError_t launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void* ws, hipStream_t st) {
   Carve c(ws);
   uint32_t* k0 = c.take<uint32_t>(n > 0 ? n : 1);
   uint32_t* k1 = c.take<uint32_t>(n > 0 ? n : 1);
   uint32_t* v0 = c.take<uint32_t>(n > 0 ? n : 1);
   uint32_t* temp = c.take<uint32_t>(radix_temp_elems(n));
-  if (n <= 0) return;
+  if (n <= 0) return hipSuccess;
   k_morton<<<(n + 255) / 256, 256, 0, st>>>(pos, n, g, k0, v0);
   uint32_t* K[2] = {k0, k1};
   uint32_t* V[2] = {v0, perm};
@@ -52,8 +52,9 @@ void launch_order(const float* pos, int n, const GridP& g, uint32_t* perm, void*
   if ((passes & 1) == 0) {
     // sort (k0, v0) -> ... -> (k0, v0), then copy v0 -> perm
     const int cur = radix_sort_pairs(K, V, 0, n, 30, temp, st);
-    if (V[cur] != perm) hipMemcpyAsync(perm, V[cur], (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
+    if (V[cur] != perm) return hipMemcpyAsync(perm, V[cur], (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, st);
   }
+  return hipSuccess;
 }
 
 }  // namespace hyrf
