@@ -183,7 +183,7 @@ def batched_views_timings(steps: int, warmup: int, cfg_name: str = "c3m_8v"):
                  mlp_geo=z(ds.mlp_geo), mlp_col=z(ds.mlp_col))
 
     def train(d, ev=None, overlap=True):
-        st = P.render(d, cams, P.TRAIN, ws=ws, events=ev)
+        st = P.render(d, cams, P.TRAIN, ws=ws, events=ev, overlap=overlap)
         loss, dL = P.l1_loss(st.image, target, ws=ws)
         for t in grads.values():
             if t is not None:
@@ -299,7 +299,7 @@ def main():
         ev.setdefault(name, []).append(e)
 
     def train_step(ev=None, dssim=False, overlap=True):
-        st = P.render(ds, cams, P.TRAIN, ws=ws, events=ev)
+        st = P.render(ds, cams, P.TRAIN, ws=ws, events=ev, overlap=overlap)
         if dssim:
             loss, dL = P.l1_dssim_loss(st.image, target, lam=0.2, ws=ws)
         else:

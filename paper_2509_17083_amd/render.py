@@ -334,19 +334,22 @@ def _mark(events, name, stream=None):
 
 
 def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False, want_keys: bool = False,
-           ws: Optional[Workspace] = None, events: Optional[dict] = None, overlap: bool = False) -> ForwardState:
+           ws: Optional[Workspace] = None, events: Optional[dict] = None, overlap: bool = True) -> ForwardState:
     """The forward render step: query -> project -> bin/sort -> composite
     (+ background).  One host read (the tile-entry count).  `events`, if
     given, collects torch.cuda.Event pairs around each ABI call.  In TRAIN
     mode with `overlap`, the background of every pixel (which needs only the
-    cameras and the fields) runs on a second stream, concurrent with the
-    Gaussian path, and is blended in at the end (off by default: both paths
-    are gather-bound, so at full size they mostly share the memory system
-    rather than overlap)."""
+    cameras and the fields) runs on a second stream once the field query
+    is done, concurrent with projection, binning and blending (the query
+    and the background are both gather-bound, so the background starts
+    after it), and is blended in at the end; the result is bit-identical."""
     lib = A.load()
     ws = ws or Workspace()
     V, W, H = len(cams), cams[0].width, cams[0].height
     split_bg = mode == TRAIN and overlap
+    _mark(events, "query0")
+    q, qout = query_fields(scene, cams, mode, debug_index, ws)
+    _mark(events, "query1")
     if split_bg:
         bg = torch.empty(V, 3, H, W, device="cuda")
         bg_feat = torch.empty(V * H * W, 2 * scene.levels, device="cuda")
@@ -362,9 +365,6 @@ def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = Fal
         _mark(events, "bg1", side)
         e_bg = torch.cuda.Event()
         e_bg.record(side)
-    _mark(events, "query0")
-    q, qout = query_fields(scene, cams, mode, debug_index, ws)
-    _mark(events, "query1")
     sp, spc = project(scene, cams, q, qout)
     _mark(events, "project1")
     n_entries = int(sp["total"].item())
