@@ -243,15 +243,27 @@ def test_render_empty_scene_is_background():
         assert res["ok"], res
 
 
-def test_train_background_on_a_second_stream_equals_one_stream():
+@pytest.mark.parametrize("cfg_name,over,n_views", [
+    ("tiny", {}, 1),
+    ("c100k", {"n_gauss": 20000, "width": 320, "height": 240, "focal": 350.0}, 3),
+])
+def test_train_background_on_a_second_stream_equals_one_stream(cfg_name, over, n_views):
+    """The train-mode forward with the background on a second stream (the
+    default) against the one-stream forward: every output bit-identical,
+    also with several views in one launch."""
+    _say("case", cfg_name, over, n_views)
     P = _P()
-    cfg, scene, cams = make("tiny", table_init=1.0)
+    cfg, scene, cams = make(cfg_name, table_init=1.0, **over)
+    if n_views > 1:
+        cams = hi.make_cameras(hi.with_overrides(cfg, n_views=n_views), seed=3004)
     scene.scale_e += np.float32(1.0)
     ds = device_scene(scene)
     a = P.render(ds, cams, P.TRAIN, overlap=True)
     b = P.render(ds, cams, P.TRAIN, overlap=False)
     torch.cuda.synchronize()
+    assert a.n_entries == b.n_entries
     assert torch.equal(a.bg, b.bg) and torch.equal(a.bg_feat, b.bg_feat) and torch.equal(a.T, b.T)
+    assert torch.equal(a.last, b.last)
     # c_fg + T c_s: one fused multiply-add in both
     assert torch.equal(a.image, b.image)
 
