@@ -98,6 +98,10 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
       const float og = q1.y * G;
       const float alpha = fminf(ALPHA_MAX, og);
       const bool contrib = (b + k) < last && power <= 0.f && alpha >= ALPHA_MIN;
+      // most splats of a batch blend into no pixel of the wave: skip them
+      // before anything else (this loop is bound by VALU issue, and the
+      // gradient registers' zeroing alone was a third of its instructions)
+      if (!__ballot(contrib)) continue;
       float gu = 0.f, gv = 0.f, ga = 0.f, gb = 0.f, gc = 0.f, go = 0.f, gr = 0.f, gg = 0.f, gbb = 0.f;
       if (contrib) {
         const float cb = s2[k].x;
@@ -126,7 +130,7 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
           gc = -0.5f * dp * dy * dy;
         }
       }
-      if (__ballot(contrib)) {
+      {
         // record fields 0..7 summed transposed (lane 2f holds field f),
         // field 8 by a plain reduction
         const float v8[8] = {gu, gv, ga, gb, gc, go, gr, gg};
