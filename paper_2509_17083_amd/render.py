@@ -189,6 +189,9 @@ class Workspace:
 
     def __init__(self):
         self.bufs: Dict[str, torch.Tensor] = {}
+        # the last train-mode forward had more tile entries per pixel than
+        # BG_LATE_ENTRIES_PER_PIXEL (see `render`)
+        self.bg_late = False
 
     def side_stream(self) -> torch.cuda.Stream:
         """A second stream (default priority) for work that overlaps the
@@ -333,26 +336,33 @@ def _mark(events, name, stream=None):
         events.setdefault(name, []).append(e)
 
 
+# Tile entries per pixel above which blending outlasts the background query
+# of every pixel (blending ~20 ps per entry, the background ~0.3 ns per pixel
+# on one MI355X), so that the train-mode background is started after binning.
+BG_LATE_ENTRIES_PER_PIXEL = 15
+
+
 def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = False, want_keys: bool = False,
            ws: Optional[Workspace] = None, events: Optional[dict] = None, overlap: bool = True) -> ForwardState:
     """The forward render step: query -> project -> bin/sort -> composite
     (+ background).  One host read (the tile-entry count).  `events`, if
     given, collects torch.cuda.Event pairs around each ABI call.  In TRAIN
     mode with `overlap`, the background of every pixel (which needs only the
-    cameras and the fields) runs on a second stream once the field query
-    is done, concurrent with projection, binning and blending (the query
-    and the background are both gather-bound, so the background starts
-    after it), and is blended in at the end; the result is bit-identical."""
+    cameras and the fields) runs on a second stream and is blended in at the
+    end; the result is bit-identical.  It starts once the field query is
+    done (both are gather-bound), beside projection, binning and blending;
+    when blending is the longer stage (more than BG_LATE_ENTRIES_PER_PIXEL
+    tile entries per pixel in the previous train-mode forward with the same
+    workspace: the count of this one is known only after projection), after
+    binning, so that it shares the CUs with blending's VALU work rather than
+    with the sort's memory streams."""
     lib = A.load()
     ws = ws or Workspace()
     V, W, H = len(cams), cams[0].width, cams[0].height
     split_bg = mode == TRAIN and overlap
-    _mark(events, "query0")
-    q, qout = query_fields(scene, cams, mode, debug_index, ws)
-    _mark(events, "query1")
-    if split_bg:
-        bg = torch.empty(V, 3, H, W, device="cuda")
-        bg_feat = torch.empty(V * H * W, 2 * scene.levels, device="cuda")
+    late_bg = split_bg and ws.bg_late
+
+    def launch_bg():
         main = torch.cuda.current_stream()
         side = ws.side_stream()
         e_start = torch.cuda.Event()
@@ -365,15 +375,29 @@ def render(scene: DeviceScene, cams, mode: int = RENDER, debug_index: bool = Fal
         _mark(events, "bg1", side)
         e_bg = torch.cuda.Event()
         e_bg.record(side)
+        return e_bg
+
+    _mark(events, "query0")
+    q, qout = query_fields(scene, cams, mode, debug_index, ws)
+    _mark(events, "query1")
+    if split_bg:
+        bg = torch.empty(V, 3, H, W, device="cuda")
+        bg_feat = torch.empty(V * H * W, 2 * scene.levels, device="cuda")
+        if not late_bg:
+            e_bg = launch_bg()
     sp, spc = project(scene, cams, q, qout)
     _mark(events, "project1")
     n_entries = int(sp["total"].item())
+    if split_bg:
+        ws.bg_late = n_entries > BG_LATE_ENTRIES_PER_PIXEL * V * W * H
     _mark(events, "bin0")
     keys, vals, ranges = bin_sort(cams, spc, max(scene.n, 1), n_entries, want_keys, ws)
     _mark(events, "bin1")
     if split_bg:
+        if late_bg:
+            e_bg = launch_bg()
         img, T, last, _, _ = composite(None, cams, spc, vals, ranges, mode, ws)
-        main.wait_event(e_bg)
+        torch.cuda.current_stream().wait_event(e_bg)
         A.check("hyrf_blend_background", lib.hyrf_blend_background(_p(bg), _p(T), _p(img), V, W, H, _stream()))
     else:
         img, T, last, bg, bg_feat = composite(scene, cams, spc, vals, ranges, mode, ws)

@@ -243,22 +243,26 @@ def test_render_empty_scene_is_background():
         assert res["ok"], res
 
 
-@pytest.mark.parametrize("cfg_name,over,n_views", [
-    ("tiny", {}, 1),
-    ("c100k", {"n_gauss": 20000, "width": 320, "height": 240, "focal": 350.0}, 3),
+@pytest.mark.parametrize("cfg_name,over,n_views,late", [
+    ("tiny", {}, 1, False),
+    ("c100k", {"n_gauss": 20000, "width": 320, "height": 240, "focal": 350.0}, 3, False),
+    ("c100k", {"n_gauss": 20000, "width": 320, "height": 240, "focal": 350.0}, 3, True),
 ])
-def test_train_background_on_a_second_stream_equals_one_stream(cfg_name, over, n_views):
+def test_train_background_on_a_second_stream_equals_one_stream(cfg_name, over, n_views, late):
     """The train-mode forward with the background on a second stream (the
     default) against the one-stream forward: every output bit-identical,
-    also with several views in one launch."""
-    _say("case", cfg_name, over, n_views)
+    also with several views in one launch, with the background started
+    after the field query or (`late`) after binning."""
+    _say("case", cfg_name, over, n_views, late)
     P = _P()
+    ws = P.Workspace()
+    ws.bg_late = late
     cfg, scene, cams = make(cfg_name, table_init=1.0, **over)
     if n_views > 1:
         cams = hi.make_cameras(hi.with_overrides(cfg, n_views=n_views), seed=3004)
     scene.scale_e += np.float32(1.0)
     ds = device_scene(scene)
-    a = P.render(ds, cams, P.TRAIN, overlap=True)
+    a = P.render(ds, cams, P.TRAIN, overlap=True, ws=ws)
     b = P.render(ds, cams, P.TRAIN, overlap=False)
     torch.cuda.synchronize()
     assert a.n_entries == b.n_entries
