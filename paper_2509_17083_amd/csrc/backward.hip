@@ -487,13 +487,15 @@ __device__ __forceinline__ void contract_vjp(const GridP& gp, float px, float py
 // per cell, corner-major: corners c and c^1 differ in x only and are adjacent
 // rows whenever the cell's x index is even, so one instruction touches a few
 // lines per cell instead of one line per float.
-constexpr int STAGE_CELLS = 28;   // run totals staged per wave and pass (4 KB per wave)
-
-struct CellStage {
-  uint32_t idx[STAGE_CELLS * 16];
-  float val[STAGE_CELLS * 16];
-  int4 cell[STAGE_CELLS];           // grid coordinates of each staged cell
+// Run totals staged per wave and pass: NC cells of 16 words (144 B each).
+template <int NC>
+struct CellStageN {
+  uint32_t idx[NC * 16];
+  float val[NC * 16];
+  int4 cell[NC];                    // grid coordinates of each staged cell
 };
+constexpr int STAGE_CELLS = 28;     // Gaussian scatters: 4 KB per wave
+using CellStage = CellStageN<STAGE_CELLS>;
 static_assert(sizeof(CellStage) <= 4096, "cell stage size");
 
 // Word of corner c (feature 0; feature 1 follows) of staged cell `slot`.
@@ -580,18 +582,18 @@ __device__ __forceinline__ void run_sums(uint64_t heads, float (&v)[N]) {
 // the original value, this cell drops it); the totals are unchanged.  Along
 // pixel rows this removes 39% of the background scatter's requests; it pays
 // where the scatter is bound by them (see the callers).
-template <bool MERGE>
+template <bool MERGE, int NC>
 __device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t heads, const int (&ci)[3],
-                                              const uint32_t (&row)[8], const float* v, CellStage& st) {
+                                              const uint32_t (&row)[8], const float* v, CellStageN<NC>& st) {
   const int lane = lane_id();
   const uint64_t tails = (heads >> 1) | (1ull << 63);
   const bool tail = (tails >> lane) & 1ull;
   const int rank = __popcll(tails & ((1ull << lane) - 1ull));
   const int K = __popcll(tails);
-  for (int b = 0; b < K; b += STAGE_CELLS) {
-    const bool mine = tail && rank >= b && rank < b + STAGE_CELLS;
+  for (int b = 0; b < K; b += NC) {
+    const bool mine = tail && rank >= b && rank < b + NC;
     const int cell = rank - b;
-    const int nc = min(K - b, STAGE_CELLS);
+    const int nc = min(K - b, NC);
     if (mine) {
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
@@ -664,10 +666,10 @@ __device__ __forceinline__ void scatter_tails(float* __restrict__ g, uint64_t he
 // One level of one table for the whole wave: the 8 corner rows and trilinear
 // weights of each lane's cell, w_c * dL/df summed over cell runs, then the
 // staged scatter.  Every lane of the wave must call it.
-template <bool MERGE>
+template <bool MERGE, int NC>
 __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t heads, const int (&ci)[3],
                                               const float (&wv)[3], float2 df, bool dense, uint32_t side,
-                                              uint32_t mask, CellStage& st) {
+                                              uint32_t mask, CellStageN<NC>& st) {
   uint32_t row[8];
   float sv[16];
 #pragma unroll
@@ -679,7 +681,7 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
     sv[2 * c + 1] = wc * df.y;
   }
   run_sums<16>(heads, sv);
-  scatter_tails<MERGE>(g, heads, ci, row, sv, st);
+  scatter_tails<MERGE, NC>(g, heads, ci, row, sv, st);
 }
 
 // Radiance-table scatter of one round of background pixels, inside the
@@ -691,10 +693,16 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
 // return; the wave's next global read waits for them (its memory counter
 // completes in issue order).
 constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
+// Cells staged per wave and pass: at the finest levels each of a wave's 64
+// pixels has a cell of its own, and every pass repeats the staging and
+// merging code for the whole wave, so the background stages more cells per
+// pass than the Gaussian scatters (5.8 KB per wave, in the dW staging space)
+constexpr int BG_STAGE_CELLS = 40;
+using BgCellStage = CellStageN<BG_STAGE_CELLS>;
 
 template <int L, bool MERGE>
 __device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, const float* sdf, const double* sx,
-                                                 CellStage& st, int w) {
+                                                 BgCellStage& st, int w) {
   static_assert(2 * L + 2 <= BG_DF_STRIDE, "LDS row too short");
   const int lane = lane_id();
   const int pl = (w & 1) * 64 + lane;
@@ -710,7 +718,7 @@ __device__ __forceinline__ void bg_round_scatter(const FieldBwdArgs& a, const fl
     float wv[3];
     grid_cell(x, res, ci, wv);
     const float2 df = *reinterpret_cast<const float2*>(sdf + pl * BG_DF_STRIDE + 2 * lev);
-    scatter_level<MERGE>(a.g_table_rad + (size_t)lev * Tr * 2, cell_heads(ci), ci, wv, df, (a.grid.dense_rad >> lev) & 1u,
+    scatter_level<MERGE, BG_STAGE_CELLS>(a.g_table_rad + (size_t)lev * Tr * 2, cell_heads(ci), ci, wv, df, (a.grid.dense_rad >> lev) & 1u,
                   (uint32_t)res + 1u, a.grid.mask_rad, st);
   }
 }
@@ -735,8 +743,10 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
   // background points run only the colour decoder: its tiles numbered from 0
   constexpr int CB = RAY ? 0 : B::TILES_GEO;
   constexpr int ACC = RAY ? (B::TILES_COL + NWV - 1) / NWV : B::template ACC<NWV>;
-  __shared__ __attribute__((aligned(16))) float Xs[PPR * STAGE_W];
-  __shared__ __attribute__((aligned(16))) float Ys[PPR * STAGE_W];
+  // the dW operand staging X (inputs) and Y (output gradients) of a round
+  __shared__ __attribute__((aligned(16))) float XY[2 * PPR * STAGE_W];
+  float* const Xs = XY;
+  float* const Ys = XY + PPR * STAGE_W;
   // the colour decoder's permuted weights (forward and adjoint operand
   // orders; float32 or bfloat16 bytes) live in LDS for the whole persistent
   // loop: every MFMA A operand is then an LDS read, not an L2 round trip
@@ -1064,24 +1074,29 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
       // background points: the round's feature gradients to LDS (the dW
       // staging is free once every wave has left the decoder adjoint), then
       // the radiance-table scatter of the round
-      static_assert(NWV == 8 && PPR * BG_DF_STRIDE <= PPR * STAGE_W && NWV * sizeof(CellStage) <= sizeof(Xs),
+      // layout in the staging space: the 8 waves' cell stages from its
+      // start, the feature gradients ([pixel][BG_DF_STRIDE]) at its end
+      constexpr int SDF_OFF = 2 * PPR * STAGE_W - PPR * BG_DF_STRIDE;
+      static_assert(NWV == 8 && NWV * sizeof(BgCellStage) <= SDF_OFF * sizeof(float) && SDF_OFF % 4 == 0,
                     "background scatter layout");
+      float* const sdf = XY + SDF_OFF;
       __syncthreads();
       const int pl = w * 16 + j;
 #pragma unroll
       for (int k = 0; k < Sh::L / 4; ++k) {
         const int lev = g + 4 * k;
-        *reinterpret_cast<float2*>(Ys + pl * BG_DF_STRIDE + 2 * lev) =
+        *reinterpret_cast<float2*>(sdf + pl * BG_DF_STRIDE + 2 * lev) =
             valid ? make_float2(dfr[2 * k], dfr[2 * k + 1]) : make_float2(0.f, 0.f);
       }
       __syncthreads();
       // shared-corner merging (the default: 39% fewer atomic requests along
       // pixel rows); the choice is uniform over the launch
       const double* sx = reinterpret_cast<const double*>(s_wf_geo) + (round & 1) * PPR * 3;
+      BgCellStage& st = reinterpret_cast<BgCellStage*>(XY)[w];
       if (a.merge)
-        bg_round_scatter<Sh::L, true>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
+        bg_round_scatter<Sh::L, true>(a, sdf, sx, st, w);
       else
-        bg_round_scatter<Sh::L, false>(a, Ys, sx, reinterpret_cast<CellStage*>(Xs)[w], w);
+        bg_round_scatter<Sh::L, false>(a, sdf, sx, st, w);
     }
   }
   write_dw<Sh, ACC, NWV, !RAY>(a.dw_part + (size_t)blockIdx.x * a.n_w, accW, w, lane);
