@@ -494,9 +494,11 @@ struct CellStageN {
   float val[NC * 16];
   int4 cell[NC];                    // grid coordinates of each staged cell
 };
-constexpr int STAGE_CELLS = 28;     // Gaussian scatters: 4 KB per wave
+// Gaussian scatters: a wave has at most 64 cells, so every level takes one
+// pass (9 KB per wave; the kernels' registers, not LDS, bound occupancy)
+constexpr int STAGE_CELLS = 64;
 using CellStage = CellStageN<STAGE_CELLS>;
-static_assert(sizeof(CellStage) <= 4096, "cell stage size");
+static_assert(sizeof(CellStage) <= 9216, "cell stage size");
 
 // Word of corner c (feature 0; feature 1 follows) of staged cell `slot`.
 __device__ __forceinline__ int stage_at(int slot, int c) { return slot * 16 + 4 * ((c >> 1) ^ (slot & 3)) + 2 * (c & 1); }
@@ -695,8 +697,8 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
 constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
 // Cells staged per wave and pass: at the finest levels each of a wave's 64
 // pixels has a cell of its own, and every pass repeats the staging and
-// merging code for the whole wave, so the background stages more cells per
-// pass than the Gaussian scatters (5.8 KB per wave, in the dW staging space)
+// merging code for the whole wave; 64 would not fit beside the feature
+// gradients in the dW staging space (40: 5.8 KB per wave)
 constexpr int BG_STAGE_CELLS = 40;
 using BgCellStage = CellStageN<BG_STAGE_CELLS>;
 
