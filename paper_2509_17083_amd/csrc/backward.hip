@@ -697,8 +697,10 @@ __device__ __forceinline__ void scatter_level(float* __restrict__ g, uint64_t he
 constexpr int BG_DF_STRIDE = 34;   // 2L + 2 floats: float2 rows spread over the LDS banks
 // Cells staged per wave and pass: at the finest levels each of a wave's 64
 // pixels has a cell of its own, and every pass repeats the staging and
-// merging code for the whole wave; 64 would not fit beside the feature
-// gradients in the dW staging space (40: 5.8 KB per wave)
+// merging code for the whole wave.  40 (5.8 KB per wave) fit beside the
+// feature gradients in the dW staging space; 64 would push the kernel's LDS
+// to 159 KB, leaving no room for the blending adjoint's workgroups that run
+// beside it on the CU
 constexpr int BG_STAGE_CELLS = 40;
 using BgCellStage = CellStageN<BG_STAGE_CELLS>;
 
