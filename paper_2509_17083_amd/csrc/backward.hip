@@ -113,22 +113,24 @@ __global__ __launch_bounds__(256) void k_composite_bwd(CompBwdArgs a) {
         gr = wgt * g0;
         gg = wgt * g1;
         gbb = wgt * g2;
-        acc0 = la * lc0 + (1.f - la) * acc0;
-        acc1 = la * lc1 + (1.f - la) * acc1;
-        acc2 = la * lc2 + (1.f - la) * acc2;
+        // colour blended behind this splat: la lc + (1 - la) acc
+        acc0 = fmaf(la, lc0 - acc0, acc0);
+        acc1 = fmaf(la, lc1 - acc1, acc1);
+        acc2 = fmaf(la, lc2 - acc2, acc2);
         lc0 = q1.z; lc1 = q1.w; lc2 = cb;
         float dLda = ((q1.z - acc0) * g0 + (q1.w - acc1) * g1 + (cb - acc2) * g2) * T;
         la = alpha;
         dLda += (-Tfin * inv1ma) * bgd;
-        if (og <= ALPHA_MAX) {
-          go = G * dLda;
-          const float dp = alpha * dLda;
-          gu = -dp * (q0.z * dx + q0.w * dy);
-          gv = -dp * (q1.x * dy + q0.w * dx);
-          ga = -0.5f * dp * dx * dx;
-          gb = -dp * dx * dy;
-          gc = -0.5f * dp * dy * dy;
-        }
+        // a clamped alpha passes no gradient on (a select, not a branch:
+        // this loop is bound by VALU issue)
+        const float dLdo = og <= ALPHA_MAX ? dLda : 0.f;
+        go = G * dLdo;
+        const float dp = alpha * dLdo;
+        gu = -dp * (q0.z * dx + q0.w * dy);
+        gv = -dp * (q1.x * dy + q0.w * dx);
+        ga = -0.5f * dp * dx * dx;
+        gb = -dp * dx * dy;
+        gc = -0.5f * dp * dy * dy;
       }
       {
         // record fields 0..7 summed transposed (lane 2f holds field f),
