@@ -542,6 +542,7 @@ static hyrf_status backward_impl(int stages, const hyrf_fields* fields, const hy
   F.merge = fields->scatter_merge == 2 ? 0 : 1;
   F.dgeo = w.dgeo;
   F.dcol = w.dcol;
+  F.n_max = sp->n_max;
   F.dfeat_geo = w.dfeat_geo;
   F.dfeat_rad = w.dfeat_rad;
   F.g_pos = grads->pos;

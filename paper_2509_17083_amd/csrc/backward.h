@@ -44,7 +44,7 @@ struct ProjBwdArgs {
   float* g_opac_e;
   float* g_col_e;
   float* dgeo;           // [n][8] to the decoder adjoint
-  float* dcol;           // [n][V][3]
+  float* dcol;           // [V][3][n_max]: planar, so that the stores coalesce
   float* dens_accum;     // [n] densification statistics, nullable
   float* dens_count;
 };
@@ -66,7 +66,8 @@ struct FieldBwdArgs {
   const float* feat_geo;
   const float* feat_rad;
   const float* dgeo;
-  const float* dcol;
+  const float* dcol;     // [V][3][n_max]
+  int n_max;
   float* dfeat_geo;      // [n][2L] feature gradients handed to the grid adjoint
   float* dfeat_rad;
   float* g_pos;

@@ -184,7 +184,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
     const int4 rc = reinterpret_cast<const int4*>(a.rect)[(size_t)v * a.n_max + s];
     if (!(rc.z > rc.x && rc.w > rc.y)) {   // no tile entries in this view: no gradient
 #pragma unroll
-      for (int c = 0; c < 3; ++c) a.dcol[((size_t)s * a.cams.V + v) * 3 + c] = 0.f;
+      for (int c = 0; c < 3; ++c) a.dcol[((size_t)v * 3 + c) * a.n_max + s] = 0.f;
       continue;
     }
     const float* gq = a.gs + ((size_t)v * a.n_max + s) * GS;
@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(ProjBwdArgs a) {
       const float col = a.rgb[((size_t)v * 3 + c) * n + s];
       const float dpre = gq[6 + c] * col * (1.f - col);
       dce[c] += dpre;
-      a.dcol[((size_t)s * a.cams.V + v) * 3 + c] = dpre;
+      a.dcol[((size_t)v * 3 + c) * a.n_max + s] = dpre;
     }
     const CamP& c = a.cams.c[v];
     double t[3];
@@ -835,7 +835,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
 #pragma unroll
         for (int k = 0; k < 4; ++k) rot_in[k] = a.rot_e ? a.rot_e[(size_t)k * a.n + gi] : 0.f;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) dcol_in[c] = a.dcol[(size_t)itc * V * 3 + c];
+        for (int c = 0; c < 3; ++c) dcol_in[c] = a.dcol[(size_t)c * a.n_max + itc];
       }
       // ---- geometry decoder adjoint
       float x1g[D::SG];
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(bwd_waves<RAY>() * 64) void k_field_bwd(FieldBwdArg
         if (v + 1 < nviews) {
           const int itc = valid ? item : 0;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) dcol_next[c] = a.dcol[((size_t)itc * V + v + 1) * 3 + c];
+          for (int c = 0; c < 3; ++c) dcol_next[c] = a.dcol[((size_t)(v + 1) * 3 + c) * a.n_max + itc];
         }
       }
       float dir[3];
