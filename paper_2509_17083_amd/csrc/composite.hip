@@ -43,25 +43,27 @@ __global__ __launch_bounds__(256) void k_composite(CompArgs a) {
     __syncthreads();
     const int nb = (int)min(256u, end - b);
     if (!done) {
+      // branch-free body (this loop is bound by VALU and SALU issue; the
+      // skips as branches cost more in execution-mask bookkeeping than the
+      // arithmetic they save): a splat that does not blend adds w = 0
       for (int k = 0; k < nb; ++k) {
         const float4 q0 = s0[k], q1 = s1[k];
         const float dx = q0.x - pxc, dy = q0.y - pyc;
         const float power = splat_power(q0.z, q0.w, q1.x, dx, dy);
-        if (power > 0.f) continue;
         const float alpha = fminf(ALPHA_MAX, q1.y * __expf(power));
-        if (alpha < ALPHA_MIN) continue;
+        const bool take = power <= 0.f && alpha >= ALPHA_MIN;
         const float tT = T * (1.f - alpha);
-        if (tT < T_EPS) {
+        if (take && tT < T_EPS) {
           done = true;
           break;
         }
-        const float w = alpha * T;
+        const float w = take ? alpha * T : 0.f;
         const float bb = s2[k].x;
         C0 = fmaf(q1.z, w, C0);
         C1 = fmaf(q1.w, w, C1);
         C2 = fmaf(bb, w, C2);
-        T = tT;
-        last = b - start + k + 1;
+        T = take ? tT : T;
+        last = take ? (uint32_t)(b - start + k + 1) : last;
       }
     }
   }
